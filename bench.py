@@ -1,0 +1,215 @@
+"""Benchmark of the coupled lattice step on one MI355X.
+
+Default workload: the buoyant bubble swarm on a 512^3 periodic box (D3Q19 +
+D3Q7), 400 bubbles with radii uniform in [8, 12] placed by seeded Poisson-disk
+sampling with a surface gap of 3, gravity 1e-6 along -z, density ratio 10,
+near-contact repulsion on, FP32 storage and arithmetic, on-device diagnostics
+every 100 steps (counted in the time).  Inputs are resident in HBM before the
+timed region starts.
+
+Prints one JSON line: throughput in MLUPS (lattice-cell updates per second of
+the whole coupled step), the roofline figure of the dominant kernel (fused
+collide + stream) measured with HIP events on the stream it runs on, and the
+CPU FP64 oracle timed on a bounded sample of the same workload.
+"""
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+METRIC = "MLUPS + % of HBM roofline per coupled step; served jobs/s + p99 latency"
+KERNEL_SRC = os.path.join(ROOT, "paper_2603_17481_amd", "csrc", "kernels.hpp")
+COUNTERS = os.path.join(ROOT, "profiles", "collide_swarm512_fp32_counters.md")
+
+# Algorithmic bytes per cell of the fused collide+stream kernel (each population
+# read once and written once, phi read once; J read only in near-contact tiles):
+#   FP32: f 19*4*2 + g 7*4*2 + phi 4 = 212 B;  FP16/BF16 f: 19*2*2 + 56 + 4 = 136 B
+#   FP64: f 19*8*2 + g 7*8*2 + phi 8 = 424 B.  J: dim * sizeof(real) per tile cell.
+COLLIDE_BYTES = {("fp32", 3): 212, ("fp16", 3): 136, ("bf16", 3): 136, ("fp64", 3): 424,
+                 ("fp32", 2): 2 * 9 * 4 * 2 + 4, ("fp64", 2): 2 * 9 * 8 * 2 + 8}
+# Whole coupled step (phi moment reads g and writes phi; collide as above):
+STEP_BYTES = {("fp32", 3): 212 + 28 + 4, ("fp16", 3): 136 + 28 + 4, ("bf16", 3): 136 + 28 + 4,
+              ("fp64", 3): 424 + 56 + 8}
+
+
+def kernel_hash() -> str:
+    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+
+
+def traffic_from_profile(n_cells):
+    """HBM bytes per collide launch from the committed rocprofv3 counter summary,
+    or None when it is missing or was taken on another version of the kernels."""
+    if not os.path.exists(COUNTERS):
+        return None
+    txt = open(COUNTERS).read()
+    m_hash = re.search(r"kernel source sha256\[:16\]: ([0-9a-f]+)", txt)
+    m_bytes = re.search(r"hbm bytes per launch: ([0-9.eE+]+)", txt)
+    if not m_hash or not m_bytes or m_hash.group(1) != kernel_hash():
+        return None
+    return float(m_bytes.group(1))
+
+
+def make_workload(args):
+    from paper_2603_17481_amd import workloads as W
+    if args.workload == "swarm":
+        st = W.config_swarm(n=args.n, bubbles=args.bubbles, precision=args.precision)
+        desc = (f"bubble swarm {args.n}^3 periodic, D3Q19+D3Q7, {args.bubbles} bubbles R~U[8,12] "
+                f"gap 3 (seed 3), g=1e-6 -z, density ratio 10, W=5, sigma=5e-3, A_rep=5e-3, "
+                f"{args.precision}, diagnostics every {args.diag} steps")
+    else:
+        st = W.config_collision_3d(precision=args.precision)
+        desc = f"droplet collision 256x128x128, D3Q19+D3Q7, {args.precision}"
+    st.params = st.params.replace(diag_interval=args.diag)
+    return st, desc
+
+
+def cpu_baseline(args):
+    """The FP64 oracle on a bounded sample of the workload: the same swarm recipe
+    on a 96^3 box (bubble count scaled with the volume), timed over a few steps."""
+    from oracle.oracle import Oracle
+    from paper_2603_17481_amd import workloads as W
+    n = args.cpu_n
+    bubbles = max(1, int(round(args.bubbles * (n / args.n) ** 3)))
+    st = W.config_swarm(n=n, bubbles=bubbles, precision="fp64")
+    o = Oracle(st.params)
+    o.init_fields(st.phi, st.u)
+    o.step(1)
+    t0 = time.perf_counter()
+    o.step(args.cpu_steps)
+    dt = time.perf_counter() - t0
+    mlups = n ** 3 * args.cpu_steps / dt / 1e6
+    return {"value": round(mlups, 3), "unit": "MLUPS", "cores": o.lib.oracle_threads(),
+            "kind": "oracle",
+            "sample": f"swarm recipe on {n}^3 ({bubbles} bubbles), FP64 oracle, {args.cpu_steps} steps, "
+                      f"{dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=300)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="swarm", choices=["swarm", "collision"])
+    ap.add_argument("--n", type=int, default=512)
+    ap.add_argument("--bubbles", type=int, default=400)
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp16", "bf16", "fp64"])
+    ap.add_argument("--diag", type=int, default=100)
+    ap.add_argument("--cpu-n", type=int, default=96)
+    ap.add_argument("--cpu-steps", type=int, default=10)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run a plain 2 GiB device copy first (reference for HBM counters)")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: the multi-GPU (domain-decomposed) path is not "
+              "built; run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2603_17481_amd import lbm
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    t_gen = time.perf_counter()
+    st, desc = make_workload(args)
+    p = st.params
+    print(f"[bench] workload ready in {time.perf_counter() - t_gen:.1f} s: {desc}", file=sys.stderr,
+          flush=True)
+    if args.copy_calibration:
+        src = torch.empty(512 * 1024 * 1024, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        src.fill_(1.0)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"[bench] copy calibration: {src.numel() * 4} bytes read, {dst.numel() * 4} written",
+              file=sys.stderr, flush=True)
+        del src, dst
+    stream = torch.cuda.Stream()
+    lat = lbm.Lattice(p, stream=stream)
+    lat.init_fields(st.phi, st.u)
+    del st
+    lat.step(args.warmup)
+    lat.sync()
+    print(f"[bench] warmup {args.warmup} steps done", file=sys.stderr, flush=True)
+
+    lat.timing(True)
+    lat.kernel_times()  # reset
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    lat.step(args.steps)
+    e1.record(stream)
+    e1.synchronize()
+    lat.sync()
+    torch.cuda.synchronize()
+    ms_total = e0.elapsed_time(e1)
+    kt = lat.kernel_times()
+    lat.timing(False)
+    print(f"[bench] timed {args.steps} steps: {ms_total:.1f} ms; kernels {kt}", file=sys.stderr,
+          flush=True)
+
+    N = p.n_cells
+    ms_step = ms_total / args.steps
+    mlups = N * args.steps / (ms_total / 1e3) / 1e6
+
+    # near-contact tiles of the final state (J is read there): from phi on the host
+    phi = lat.phi()
+    pc = np.clip(phi, 0, 1)
+    gated = pc * (1 - pc) >= p.q_th
+    t = 8 if p.precision != "fp64" else 4
+    tiles = gated.reshape(p.nz // t, t, p.ny // 8, 8, p.nx // 8, 8).any(axis=(1, 3, 5)).sum()
+    tile_cells = int(tiles) * 8 * 8 * t
+    real = 8 if p.precision == "fp64" else 4
+    bytes_launch = COLLIDE_BYTES[(p.precision, p.dim)] * N + p.dim * real * tile_cells
+    coll_ms, coll_n = kt["collide"]
+    avg_s = coll_ms / coll_n / 1e3
+    achieved = bytes_launch / avg_s / 1e9
+    traffic = traffic_from_profile(N)
+    diag = lat.diagnostics()
+    out = {
+        "metric": METRIC,
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"fp32": "f32", "fp64": "f64", "fp16": "f16-store/f32", "bf16": "bf16-store/f32"}[p.precision],
+        "data": "synthetic",
+        "config": {"workload": desc, "cells": N, "global_batch": 1, "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
+                     "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
+                     "traffic": traffic, "kernel": "k_collide (fused collide+stream)",
+                     "bytes_per_launch": bytes_launch,
+                     "avg_launch_ms": round(avg_s * 1e3, 4),
+                     "step_model_bytes_per_cell": STEP_BYTES.get((p.precision, p.dim)),
+                     "step_frac": round(STEP_BYTES.get((p.precision, p.dim), 0) * N / (ms_step / 1e3) / 1e9
+                                        / PEAK_HBM_GBS, 4)},
+        "kernel_ms_per_launch": {k: round(v[0] / max(v[1], 1), 4) for k, v in kt.items()},
+        "state": {"step": diag["step"], "n_bubbles": diag["n_droplets"], "nci_active": diag["nci_active"],
+                  "finite": diag["finite"], "mass_phi": diag["mass_phi"]},
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(args)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

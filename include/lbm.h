@@ -1,0 +1,188 @@
+/*
+ * lbm.h -- C ABI of the MI355X (gfx950) coupled lattice step.
+ *
+ * One time step couples three pieces of arXiv:2603.17481 ("Adaptive
+ * near-contact repulsion in conservative Allen-Cahn phase-field lattice
+ * Boltzmann multiphase model"):
+ *   - recursive-regularised lattice Boltzmann hydrodynamics with a third-order
+ *     equilibrium and Guo forcing in the velocity / p* formulation
+ *     (Sec. 2.1: Eqs. lbe, nuomega, pstar, pstar_moment, u_moment,
+ *     mu_mix_linear, nu_from_mu, omega_phi, feq3, H2, H3, fneq3, A3rec, guo,
+ *     Fsplit, Fcap, Fp, Fnu, grad_iso, lap_iso), on D2Q9 (2D) or D3Q19 (3D);
+ *   - the conservative Allen-Cahn equation (Sec. 2.1.1, Eqs. cace,
+ *     cace_conservative, normal, kappa_delta) advanced by a lattice Boltzmann
+ *     equation on D2Q9 (2D) or D3Q7 (3D) whose equilibrium carries the
+ *     counter-gradient flux M (4/W) phi (1 - phi) n in its first moment;
+ *   - the near-contact repulsion: interfacial gate, windowed partner search
+ *     and the closed-form film-thickness weight (Sec. 2.2, Sec. 2.3: Eqs.
+ *     n_discrete, q_discrete, q_gate, window, q_similarity, facing_threshold,
+ *     facing_score, mask_partner_def, qpair_impl, q_clamp, face_impl,
+ *     nsym_impl, h_impl, wh_impl, Jrep_impl, Frep_impl).
+ *
+ * Conventions for every entry point:
+ *   - Cells are indexed idx = x + nx * (y + ny * z); the box is periodic in
+ *     every direction; in 2D nz = 1.  Node i sits at coordinate i.
+ *   - Host arrays are owned by the caller, are always double precision
+ *     whatever the compute precision, and are copied synchronously.
+ *     Vector fields are structure-of-arrays: component a of cell idx at
+ *     [a * N + idx].
+ *   - Every call returns an LBM_* code; the message of the last failure of a
+ *     context is returned by lbm_last_error(ctx) (lbm_last_error(NULL) for a
+ *     failed lbm_create).  Nothing throws across the ABI and nothing aborts.
+ *   - A context is bound to the HIP device that was current at lbm_create and
+ *     to one stream; it is not thread-safe.  Separate contexts are independent.
+ *   - The library needs a gfx950 device; it never falls back to the CPU.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  LBM_OK = 0,
+  LBM_E_INVALID = -1,     /* bad argument or parameter                         */
+  LBM_E_OOM = -2,         /* device allocation failed / workspace too small    */
+  LBM_E_HIP = -3,         /* HIP runtime error                                 */
+  LBM_E_UNSUPPORTED = -4, /* combination not built                             */
+  LBM_E_DIVERGED = -5,    /* non-finite value seen by a periodic diagnostic    */
+  LBM_E_STATE = -6        /* call out of order (e.g. step before init)         */
+};
+
+/* Storage / arithmetic of the populations.  FP16 and BF16 store the
+ * hydrodynamic populations as d_i = f_i - w_i pstar_ref in 16 bits and do all
+ * arithmetic in FP32; the phase-field populations stay FP32. */
+enum { LBM_FP64 = 0, LBM_FP32 = 1, LBM_FP32_F16STORE = 2, LBM_FP32_BF16STORE = 3 };
+
+typedef struct {
+  int dim, nx, ny, nz;       /* dim 2 => nz must be 1                                      */
+  int precision;             /* LBM_FP64 ... LBM_FP32_BF16STORE                            */
+  double tau;                /* liquid relaxation time: nu_l = cs^2 (tau - 1/2), Eq. nuomega */
+  double visc_ratio;         /* nu_g / nu_l (kinematic)                                     */
+  double mobility;           /* M = D of Eq. cace; tau_phi = 1/2 + M / cs_phi^2             */
+  double width;              /* W = epsilon = delta, interface thickness                    */
+  double sigma;              /* surface tension                                             */
+  double density_ratio;      /* rho_l / rho_g with rho_l = 1 (phi = 1 phase)                */
+  double a_rep;              /* A_rep of Eq. Jrep_impl; 0 turns the near-contact force off  */
+  double body_force[3];      /* g; F_ext = (rho - <rho>) g, <rho> the box mean              */
+  int nci_window;            /* w of Eq. window (1, 2 or 3)                                 */
+  double q_th, eta, cos_opp; /* Eqs. q_gate, q_similarity, facing_threshold                 */
+  double h0, p_exp;          /* w_h = 1 / (1 + (h/h0)^p), Eq. wh_general                    */
+  double eps_n, eps_q;       /* regularisations of Eqs. n_discrete, q_similarity, q_clamp   */
+  double tie_eps;            /* partner choice: among candidates at the smallest |r|^2,
+                                facing scores within tie_eps of the best are tied and the
+                                first in scan order (dz, dy, dx from -w) wins              */
+  int rep_orient;            /* n_sym orientation: 0 along n(x) (planar-limit form of
+                                Sec. 2.2.5), +1 toward the partner, -1 away from it         */
+  int dispersed;             /* droplet count of {phi > 1/2} (1) or {phi < 1/2} (0);
+                                -1 picks the minority phase at initialisation              */
+  int cac_compress;          /* 1: counter-gradient flux on; 0: off (pure diffusion)        */
+  int diag_interval;         /* K > 0: on-device diagnostics every K steps inside lbm_step  */
+  double pstar_ref;          /* reference p* of the 16-bit population encoding              */
+} lbm_params;
+
+typedef struct {
+  long step;                 /* state the numbers describe                                  */
+  double mass_phi;           /* sum phi (FP64 accumulation)                                 */
+  double sum_pstar;          /* sum p*                                                      */
+  double momentum[3];        /* sum rho u                                                   */
+  double kinetic_energy;     /* sum rho |u|^2 / 2                                           */
+  double max_speed;          /* max |u|                                                     */
+  long n_droplets;           /* Euler characteristic of the dispersed set (8-/26-connected
+                                closed-voxel union): the droplet / bubble count while each
+                                one is simply connected                                    */
+  long nci_active;           /* number of cells with chi_nc = 1                             */
+  int finite;                /* 1 if every p*, u and phi is finite                          */
+} lbm_diag;
+
+typedef struct lbm_ctx lbm_ctx;
+
+/* Fill *p with the defaults: 2D 128x128 FP64, tau 1, M 0.1, W 4, sigma 1e-3,
+ * density ratio 1, A_rep 1e-3 and the detection parameters of Sec. 2.3.2
+ * (w 3, q_th 0.125, eta 0.1, cos_opp -0.8) and Sec. 2.3.3 (h0 1, p 4). */
+void lbm_default_params(lbm_params* p);
+
+/* Bytes of device workspace a context with these parameters needs (all state
+ * that stays resident: populations, phi, the repulsive flux, tile lists,
+ * reduction scratch).  0 if the parameters are invalid. */
+size_t lbm_workspace_bytes(const lbm_params* p);
+
+/* Create a context on the current HIP device.  dev_workspace: NULL lets the
+ * library allocate; otherwise a device pointer of at least
+ * lbm_workspace_bytes(p) bytes, 256-byte aligned, that the caller keeps alive
+ * until lbm_destroy (e.g. a torch tensor).  hip_stream: a hipStream_t, or
+ * NULL for a stream the library creates.  Returns LBM_E_INVALID,
+ * LBM_E_OOM or LBM_E_HIP on failure, with *out = NULL. */
+int lbm_create(const lbm_params* p, void* dev_workspace, size_t ws_bytes, void* hip_stream,
+               lbm_ctx** out);
+void lbm_destroy(lbm_ctx* ctx);
+const char* lbm_last_error(const lbm_ctx* ctx);
+
+/* Initial state: f = feq(p*, u) (Eq. feq3), g = geq(phi, u, n).  phi: N
+ * doubles; u: dim*N (NULL = at rest); pstar: N (NULL = pstar_ref).  Resets the
+ * step count to 0.  Synchronous. */
+int lbm_init_fields(lbm_ctx* ctx, const double* phi, const double* u, const double* pstar);
+
+/* Enqueue n coupled steps on the context's stream (asynchronous). */
+int lbm_step(lbm_ctx* ctx, int n);
+/* Wait for the stream; LBM_E_DIVERGED if a periodic diagnostic saw a
+ * non-finite value since the last lbm_init_fields / lbm_load_state. */
+int lbm_sync(lbm_ctx* ctx);
+long lbm_step_count(const lbm_ctx* ctx);
+
+/* Fields of the current state, recomputed from the populations (synchronous). */
+int lbm_get_phi(lbm_ctx* ctx, double* out_N);
+int lbm_get_rho(lbm_ctx* ctx, double* out_N);
+int lbm_get_pstar(lbm_ctx* ctx, double* out_N);
+int lbm_get_u(lbm_ctx* ctx, double* out_dimN);     /* u = m + F / (2 rho), Eq. u_moment */
+int lbm_get_force(lbm_ctx* ctx, double* out_dimN); /* total F of Eq. Fsplit            */
+/* Near-contact state of the current step: chi (N ints, NULL to skip),
+ * partner offsets (3*N ints, SoA dx/dy/dz, NULL to skip) and J_rep (dim*N). */
+int lbm_get_nci(lbm_ctx* ctx, int* chi, int* partner, double* J);
+/* Diagnostics of the current state (synchronous, FP64). */
+int lbm_diagnostics(lbm_ctx* ctx, lbm_diag* out);
+/* Diagnostics recorded every diag_interval steps by lbm_step, oldest first;
+ * at most max entries (the last 64 are kept).  Returns the count or <0. */
+int lbm_diag_history(lbm_ctx* ctx, lbm_diag* out, int max);
+
+/* Per-kernel timing with HIP events recorded on the context's stream around
+ * every launch lbm_step makes (0 phi moment, 1 near-contact, 2 collide +
+ * stream, 3 diagnostics).  lbm_timing(ctx, 1) starts recording, 0 stops;
+ * lbm_kernel_times synchronises, returns the accumulated milliseconds and
+ * launch counts since the last call (ms[4], counts[4]) and resets them. */
+int lbm_timing(lbm_ctx* ctx, int enable);
+int lbm_kernel_times(lbm_ctx* ctx, double* ms, long* counts);
+
+/* Lattice velocity order used by the population calls: which 0 = hydrodynamic
+ * lattice, 1 = phase-field lattice of a dim-dimensional context; c receives
+ * 3*q ints (cx, cy, cz per velocity).  Returns q. */
+int lbm_lattice(int dim, int which, int* c);
+/* Incoming populations of the current state on the periodic box
+ * [x0, x0+bx) x [y0, y0+by) x [z0, z0+bz) (wrapped), SoA [q][bz][by][bx]. */
+int lbm_get_populations(lbm_ctx* ctx, int x0, int y0, int z0, int bx, int by, int bz,
+                        double* f, double* g);
+/* Replace the whole state by the given incoming populations (SoA [q][N]); the
+ * step count becomes 0.  Synchronous. */
+int lbm_set_populations(lbm_ctx* ctx, const double* f, const double* g);
+
+/* Raw state (populations in their stored precision and AA layout, step count)
+ * for checkpoint / restart; a restored context continues bit for bit. */
+size_t lbm_state_bytes(const lbm_ctx* ctx);
+int lbm_save_state(lbm_ctx* ctx, void* host_buf, size_t bytes);
+int lbm_load_state(lbm_ctx* ctx, const void* host_buf, size_t bytes);
+
+/* Serving: advance every context by n steps with multi-domain launches that
+ * cover all of them at once (kernels loop over a device job table), replayed
+ * from a cached HIP graph.  All contexts must live on the same device, share
+ * dimension and precision, and be initialised.  Their results equal those of
+ * lbm_step on each alone.  Enqueued on the first context's stream; the others'
+ * streams are synchronised first.  Asynchronous. */
+int lbm_batch_step(lbm_ctx* const* ctxs, int count, int n);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

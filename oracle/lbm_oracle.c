@@ -234,7 +234,9 @@ static long wrapi(long i, long n) {
  * scanned with dz outermost, then dy, then dx, each from -w to +w.
  * Accept: q(y) >= q_th; |q(y)-q(x)| <= eta max(q(x), eps_q); n(x).n(y) <= cos_opp.
  * Choose the smallest |r|^2; among equal |r|^2 the largest facing score
- * (smallest n(x).n(y)); remaining ties keep the first in scan order. */
+ * (smallest n(x).n(y)); scores within tie_eps of that best count as tied and
+ * the first of them in scan order is taken, so that rounding-level differences
+ * in n cannot flip the choice between mirror-image candidates. */
 int oracle_nci_from_qn(const oracle_params* P, const double* q, const double* n, int* chi,
                        int* partner, double* J) {
   const int D = P->dim;
@@ -253,33 +255,44 @@ int oracle_nci_from_qn(const oracle_params* P, const double* q, const double* n,
     if (!(qx >= P->q_th)) continue; /* interfacial gate, Eq. q_gate */
     double nxv[3] = {0, 0, 0};
     for (int a = 0; a < D; ++a) nxv[a] = n[a * N + idx];
+    /* Pass 1: accepted candidates (three tests of Sec. 2.3.2); smallest |r|^2 and,
+     * among those, the smallest n(x).n(y) (largest facing score). */
     int found = 0, best[3] = {0, 0, 0};
     long best_d2 = 0;
     double best_dot = 0.0;
     long best_idx = -1;
-    for (int dz = -wz; dz <= wz; ++dz)
-      for (int dy = -w; dy <= w; ++dy)
-        for (int dx = -w; dx <= w; ++dx) {
-          if (dx == 0 && dy == 0 && dz == 0) continue;
-          long jdx = wrapi(x + dx, nx) + nx * (wrapi(y + dy, ny) + ny * wrapi(z + dz, nz));
-          double qy = q[jdx];
-          if (!(qy >= P->q_th)) continue;                                    /* neighbour gate */
-          double qmax = qx > P->eps_q ? qx : P->eps_q;
-          if (!(fabs(qy - qx) <= P->eta * qmax)) continue;                   /* Eq. q_similarity */
-          double dot = 0.0;
-          for (int a = 0; a < D; ++a) dot += nxv[a] * n[a * N + jdx];
-          if (!(dot <= P->cos_opp)) continue;                                /* Eq. facing_threshold */
-          long d2 = (long)dx * dx + (long)dy * dy + (long)dz * dz;
-          if (!found || d2 < best_d2 || (d2 == best_d2 && dot < best_dot)) {
-            found = 1;
-            best_d2 = d2;
-            best_dot = dot;
-            best[0] = dx;
-            best[1] = dy;
-            best[2] = dz;
-            best_idx = jdx;
+    for (int pass = 0; pass < 2; ++pass) {
+      for (int dz = -wz; dz <= wz; ++dz)
+        for (int dy = -w; dy <= w; ++dy)
+          for (int dx = -w; dx <= w; ++dx) {
+            if (dx == 0 && dy == 0 && dz == 0) continue;
+            long jdx = wrapi(x + dx, nx) + nx * (wrapi(y + dy, ny) + ny * wrapi(z + dz, nz));
+            double qy = q[jdx];
+            if (!(qy >= P->q_th)) continue;                                    /* neighbour gate */
+            double qmax = qx > P->eps_q ? qx : P->eps_q;
+            if (!(fabs(qy - qx) <= P->eta * qmax)) continue;                   /* Eq. q_similarity */
+            double dot = 0.0;
+            for (int a = 0; a < D; ++a) dot += nxv[a] * n[a * N + jdx];
+            if (!(dot <= P->cos_opp)) continue;                                /* Eq. facing_threshold */
+            long d2 = (long)dx * dx + (long)dy * dy + (long)dz * dz;
+            if (pass == 0) {
+              if (!found || d2 < best_d2 || (d2 == best_d2 && dot < best_dot)) {
+                found = 1;
+                best_d2 = d2;
+                best_dot = dot;
+              }
+            } else if (best_idx < 0 && d2 == best_d2 && dot <= best_dot + P->tie_eps) {
+              /* Pass 2: the first candidate in scan order whose facing score ties the
+               * best within tie_eps. */
+              best[0] = dx;
+              best[1] = dy;
+              best[2] = dz;
+              best_idx = jdx;
+              best_dot = dot;
+            }
           }
-        }
+      if (!found) break;
+    }
     if (!found) continue;
     chi[idx] = 1; /* Eq. mask_partner_def */
     for (int a = 0; a < 3; ++a) partner[a * N + idx] = best[a];
@@ -585,11 +598,51 @@ static void collide_and_push(oracle_state* s) {
   s->g2 = t;
 }
 
+/* Test knob (not part of the method): round the stored populations after each
+ * step to a narrower format, to measure how the method amplifies storage
+ * rounding.  mode 1: float32; 2: IEEE half; 3: bfloat16 (f only for 2 and 3;
+ * g stays float32 there).  Round to nearest even in every case. */
+static double round_to(double v, int mode) {
+  if (mode == 1) return (double)(float)v;
+  if (mode == 2) {
+    /* IEEE binary16: 11 significant bits, smallest normal 2^-14, subnormal
+     * spacing 2^-24; nearbyint rounds half to even. */
+    if (v == 0.0 || !isfinite(v)) return v;
+    int E;
+    double a = fabs(v);
+    frexp(a, &E); /* a in [2^(E-1), 2^E) */
+    int ue = E - 11;
+    if (ue < -24) ue = -24;
+    double r = ldexp(nearbyint(ldexp(a, -ue)), ue);
+    if (r > 65504.0) r = INFINITY;
+    return v < 0 ? -r : r;
+  }
+  if (mode == 3) {
+    float f = (float)v;
+    unsigned int b;
+    memcpy(&b, &f, 4);
+    unsigned int lsb = (b >> 16) & 1u;
+    b = (b + 0x7fffu + lsb) & 0xffff0000u;
+    memcpy(&f, &b, 4);
+    return (double)f;
+  }
+  return v;
+}
+
+static void round_storage(oracle_state* s) {
+  const int mode = s->P.store_round;
+  if (mode <= 0) return;
+  const long nf = s->N * s->LF.q, ng = s->N * s->LG.q;
+  for (long i = 0; i < nf; ++i) s->f[i] = round_to(s->f[i], mode);
+  for (long i = 0; i < ng; ++i) s->g[i] = round_to(s->g[i], 1);
+}
+
 int oracle_step(oracle_state* s, int n) {
   if (!s || n < 0) return -1;
   for (int k = 0; k < n; ++k) {
     compute_fields(s);
     collide_and_push(s);
+    round_storage(s);
     s->step++;
   }
   return 0;
@@ -632,6 +685,7 @@ int oracle_init_fields(oracle_state* s, const double* phi, const double* u, cons
     }
   }
   set_rho_mean(s);
+  round_storage(s);
   s->step = 0;
   return 0;
 }

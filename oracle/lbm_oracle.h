@@ -29,9 +29,12 @@ typedef struct {
   double body_force[3];    /* g; F_ext = (rho - <rho>) g                                */
   int nci_window;          /* w                                                         */
   double q_th, eta, cos_opp, h0, p_exp, eps_n, eps_q;
+  double tie_eps;          /* facing scores within tie_eps of the best count as tied  */
   int rep_orient;          /* 0: along n(x); +1: toward partner; -1: away from partner  */
   int dispersed;           /* 1: droplets {phi>1/2}; 0: bubbles {phi<1/2}; -1: auto     */
   int cac_compress;        /* 1: counter-gradient flux on; 0: off (pure diffusion)       */
+  int store_round;         /* test knob: 0 none; round stored populations after each
+                              step to 1 float32, 2 half (f), 3 bfloat16 (f)            */
 } oracle_params;
 
 typedef struct {

@@ -24,7 +24,9 @@ class _Params(C.Structure):
         ("nci_window", C.c_int),
         ("q_th", C.c_double), ("eta", C.c_double), ("cos_opp", C.c_double), ("h0", C.c_double),
         ("p_exp", C.c_double), ("eps_n", C.c_double), ("eps_q", C.c_double),
+        ("tie_eps", C.c_double),
         ("rep_orient", C.c_int), ("dispersed", C.c_int), ("cac_compress", C.c_int),
+        ("store_round", C.c_int),
     ]
 
 
@@ -94,7 +96,7 @@ def _iptr(a: Optional[np.ndarray]):
     return a.ctypes.data_as(C.POINTER(C.c_int))
 
 
-def make_params(p) -> _Params:
+def make_params(p, store_round: int = 0) -> _Params:
     s = _Params()
     s.dim, s.nx, s.ny = p.dim, p.nx, p.ny
     s.nz = p.nz if p.dim == 3 else 1
@@ -105,7 +107,9 @@ def make_params(p) -> _Params:
     s.nci_window = p.nci_window
     s.q_th, s.eta, s.cos_opp, s.h0 = p.q_th, p.eta, p.cos_opp, p.h0
     s.p_exp, s.eps_n, s.eps_q = p.p_exp, p.eps_n, p.eps_q
+    s.tie_eps = p.tie_eps
     s.rep_orient, s.dispersed, s.cac_compress = p.rep_orient, p.dispersed, p.cac_compress
+    s.store_round = int(store_round)
     return s
 
 
@@ -123,10 +127,12 @@ def lattice(kind: int):
 class Oracle:
     """One lattice on the CPU oracle.  Arrays follow Params.shape (x fastest)."""
 
-    def __init__(self, params):
+    def __init__(self, params, store_round: int = 0):
+        """store_round (test knob): 0 exact; 1/2/3 round the stored populations to
+        float32 / half / bfloat16 after every step (sensitivity measurements)."""
         self.lib = load()
         self.params = params
-        self._p = make_params(params)
+        self._p = make_params(params, store_round)
         self.h = self.lib.oracle_create(C.byref(self._p))
         if not self.h:
             raise RuntimeError("oracle_create failed")

@@ -1,0 +1,778 @@
+// kernels.hpp -- HIP kernels of the coupled lattice step for gfx950.
+//
+// Per step (AA pattern, parity p = step mod 2, one population array per lattice):
+//   k_phi      phi = sum_k g_k gathered with the AA parity; flags the near-contact
+//              tiles that hold an interfacial cell (q >= q_th) and lists them.
+//   k_nci      for listed tiles only: LDS phi tile with a halo of 4, normals and
+//              indicator on tile + 3, partner search in the (2w+1)^d window and
+//              the repulsive flux J (Sec. 2.3) written for every cell of the tile.
+//   k_collide  fused hydrodynamic + phase-field collide and stream, in place,
+//              structure-of-arrays; reads J only in flagged tiles.
+//   k_diag     FP64 sums of phi and the Euler characteristic of the dispersed set.
+// Grids are 1-D with an XCD-aware block swizzle: consecutive tiles of the domain
+// land on the same XCD so that stencil re-reads hit its L2.
+#pragma once
+
+#include <hip/hip_bf16.h>
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+
+#include "lattice.hpp"
+
+namespace lbm {
+
+constexpr int BX = 64;   // cells along x per block (one wave)
+constexpr int BY = 4;    // rows per block
+constexpr int NT = BX * BY;
+constexpr int PHI_HALO = 4;   // window radius 3 + 1 for the normals
+constexpr int NQ_HALO = 3;    // window radius
+constexpr int NPART = 8;      // doubles per block in the reduction scratch
+
+struct Geo {
+  int nx, ny, nz;
+  int nbx, nby;          // blocks along x and y (BX x BY cells each)
+  long long S;           // plane stride of the structure-of-arrays fields
+  int ntx, nty, ntz;     // near-contact tiles along x, y, z
+};
+
+struct Phys {
+  double rho_g, drho;    // rho = rho_g + drho phi
+  double mu_a, mu_b;     // dynamic viscosity rho nu = mu_a + mu_b phi
+  double beta4, kappa;   // mu_phi = beta4 phi (phi-1)(phi-1/2) - kappa lap phi
+  double rho_mean;       // box mean of rho (for the buoyancy force)
+  double g[3];
+  double kc;             // M 4 / W (0 when the counter-gradient flux is off)
+  double inv_tau_phi;    // 1 / (1/2 + M / cs_phi^2)
+  double pstar_ref;      // reference p* of the 16-bit population encoding
+  double eps_n;          // regularisation of the normal n = grad phi / (|grad phi| + eps_n)
+};
+
+struct NciP {
+  double a_rep, q_th, eta, cos_opp, h0, p_exp, eps_n, eps_q, width, tie_eps;
+  int w, orient;
+};
+
+// Near-contact tile of each (dimension, precision); the FP64 tile is thinner so
+// that its LDS footprint stays below 96 KB.
+template <int DIM, typename T>
+struct NciTile;
+template <typename T>
+struct NciTile<2, T> {
+  static constexpr int TX = 16, TY = 16, TZ = 1;
+};
+template <>
+struct NciTile<3, float> {
+  static constexpr int TX = 8, TY = 8, TZ = 8;
+};
+template <>
+struct NciTile<3, double> {
+  static constexpr int TX = 8, TY = 8, TZ = 4;
+};
+
+// ---------------------------------------------------------------------------
+// small helpers
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ int swizzled_block() {
+  const int b = blockIdx.x, n = gridDim.x;
+  const int full = n & ~7;
+  return b < full ? (b & 7) * (n >> 3) + (b >> 3) : b;
+}
+
+__device__ __forceinline__ int wrapi(int i, int n) {
+  int r = i % n;
+  return r < 0 ? r + n : r;
+}
+
+template <typename S>
+struct Store;
+template <>
+struct Store<double> {
+  __device__ static double ld(const double* p, double) { return *p; }
+  __device__ static void st(double* p, double v, double) { *p = v; }
+};
+template <>
+struct Store<float> {
+  __device__ static float ld(const float* p, float) { return *p; }
+  __device__ static void st(float* p, float v, float) { *p = v; }
+};
+template <>
+struct Store<__half> {
+  __device__ static float ld(const __half* p, float off) { return __half2float(*p) + off; }
+  __device__ static void st(__half* p, float v, float off) { *p = __float2half_rn(v - off); }
+};
+template <>
+struct Store<__hip_bfloat16> {
+  __device__ static float ld(const __hip_bfloat16* p, float off) { return __bfloat162float(*p) + off; }
+  __device__ static void st(__hip_bfloat16* p, float v, float off) { *p = __float2bfloat16(v - off); }
+};
+
+__device__ __forceinline__ float m_sqrt(float a) { return sqrtf(a); }
+__device__ __forceinline__ double m_sqrt(double a) { return sqrt(a); }
+__device__ __forceinline__ float m_acosh(float a) { return acoshf(a); }
+__device__ __forceinline__ double m_acosh(double a) { return acosh(a); }
+__device__ __forceinline__ float m_pow(float a, float b) { return powf(a, b); }
+__device__ __forceinline__ double m_pow(double a, double b) { return pow(a, b); }
+__device__ __forceinline__ float m_abs(float a) { return fabsf(a); }
+__device__ __forceinline__ double m_abs(double a) { return fabs(a); }
+
+// Periodic neighbours of a cell: index of x + (dx, dy, dz), |d| <= 1.
+struct Nbr {
+  int xs[3];
+  int ys[3];      // nx * y'
+  long long zs[3];  // nx * ny * z'  (kept 64-bit to be safe; converted on use)
+  __device__ Nbr(int x, int y, int z, const Geo& g) {
+    xs[0] = x == 0 ? g.nx - 1 : x - 1;
+    xs[1] = x;
+    xs[2] = x == g.nx - 1 ? 0 : x + 1;
+    ys[0] = g.nx * (y == 0 ? g.ny - 1 : y - 1);
+    ys[1] = g.nx * y;
+    ys[2] = g.nx * (y == g.ny - 1 ? 0 : y + 1);
+    const long long pl = (long long)g.nx * g.ny;
+    zs[0] = pl * (z == 0 ? g.nz - 1 : z - 1);
+    zs[1] = pl * z;
+    zs[2] = pl * (z == g.nz - 1 ? 0 : z + 1);
+  }
+  __device__ __forceinline__ int operator()(int dx, int dy, int dz) const {
+    return xs[dx + 1] + ys[dy + 1] + (int)zs[dz + 1];
+  }
+};
+
+// Isotropic gradient and Laplacian with the hydrodynamic lattice weights
+// (Eqs. grad_iso, lap_iso; 1/cs^2 = 3).  get(i) returns psi(x + c_i).
+template <int DIM, typename T, typename G>
+__device__ __forceinline__ void grad_lap(const G& get, T gr[3], T& lap) {
+  using L = Hydro<DIM>;
+  T g0 = 0, g1 = 0, g2 = 0, sn = 0;
+#pragma unroll
+  for (int i = 1; i < L::Q; i += 2) {
+    const T a = get(i), b = get(i + 1);
+    const T w = wt<L, T>(i);
+    const T d = w * (a - b);
+    if (L::cx[i]) g0 += L::cx[i] > 0 ? d : -d;
+    if (L::cy[i]) g1 += L::cy[i] > 0 ? d : -d;
+    if (DIM == 3 && L::cz[i]) g2 += L::cz[i] > 0 ? d : -d;
+    sn += w * (a + b);
+  }
+  gr[0] = (T)3 * g0;
+  gr[1] = (T)3 * g1;
+  gr[2] = DIM == 3 ? (T)3 * g2 : (T)0;
+  lap = (T)6 * (sn - ((T)1 - wt<L, T>(0)) * get(0));
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+template <typename T>
+__device__ __forceinline__ T wave_max(T v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    T u = __shfl_xor(v, o, 64);
+    v = u > v ? u : v;
+  }
+  return v;
+}
+
+// ---------------------------------------------------------------------------
+// (a1) phi moment of the phase-field populations
+// ---------------------------------------------------------------------------
+
+template <int DIM, int PAR, typename T, typename GS>
+__global__ __launch_bounds__(NT) void k_phi(const GS* __restrict__ g, T* __restrict__ phi, Geo geo,
+                                            unsigned* __restrict__ flags,
+                                            unsigned* __restrict__ list,
+                                            unsigned* __restrict__ cnt,
+                                            unsigned* __restrict__ nci_count, int nci_on, T q_th,
+                                            int ttx, int tty, int ttz) {
+  using P = Phase<DIM>;
+  if (nci_on && blockIdx.x == 0 && threadIdx.x == 0) *nci_count = 0u;
+  const int t = swizzled_block();
+  const int bx = t % geo.nbx, r = t / geo.nbx, by = r % geo.nby, z = r / geo.nby;
+  const int x = bx * BX + (int)(threadIdx.x & (BX - 1)), y = by * BY + (int)(threadIdx.x / BX);
+  if (x >= geo.nx || y >= geo.ny) return;
+  const int idx = x + geo.nx * (y + geo.ny * z);
+  // accumulated in FP64 (exact for FP32 populations), rounded once
+  double acc = 0.0;
+  if constexpr (PAR == 0) {
+#pragma unroll
+    for (int i = 0; i < P::Q; ++i) acc += (double)g[i * geo.S + idx];
+  } else {
+    const Nbr nb(x, y, z, geo);
+#pragma unroll
+    for (int i = 0; i < P::Q; ++i) acc += (double)g[opp(i) * geo.S + nb(-P::cx[i], -P::cy[i], -P::cz[i])];
+  }
+  const T s = (T)acc;
+  phi[idx] = s;
+  if (nci_on) {
+    const T pc = s < (T)0 ? (T)0 : (s > (T)1 ? (T)1 : s);
+    const T q = pc * ((T)1 - pc);
+    if (q >= q_th) {
+      const unsigned tile = (unsigned)(x / ttx + geo.ntx * (y / tty + geo.nty * (z / ttz)));
+      if (flags[tile] == 0u && atomicExch(&flags[tile], 1u) == 0u) list[atomicAdd(cnt, 1u)] = tile;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// (a2) near-contact detection, pairing and repulsive flux (Sec. 2.3)
+// ---------------------------------------------------------------------------
+
+template <int DIM, typename T, bool DEBUG>
+__global__ __launch_bounds__(NT) void k_nci(const T* __restrict__ phi, T* __restrict__ J,
+                                            int* __restrict__ chi_out, int* __restrict__ part_out,
+                                            const unsigned* __restrict__ list,
+                                            const unsigned* __restrict__ cnt,
+                                            unsigned* __restrict__ flags_other,
+                                            const unsigned* __restrict__ list_other,
+                                            const unsigned* __restrict__ cnt_other,
+                                            unsigned* __restrict__ nci_count, Geo geo, NciP np) {
+  using TL = NciTile<DIM, T>;
+  using L = Hydro<DIM>;
+  constexpr int TX = TL::TX, TY = TL::TY, TZ = TL::TZ;
+  constexpr int PX = TX + 2 * PHI_HALO, PY = TY + 2 * PHI_HALO, PZ = DIM == 3 ? TZ + 2 * PHI_HALO : 1;
+  constexpr int NX = TX + 2 * NQ_HALO, NY = TY + 2 * NQ_HALO, NZ = DIM == 3 ? TZ + 2 * NQ_HALO : 1;
+  constexpr int NPH = PX * PY * PZ, NNQ = NX * NY * NZ;
+  __shared__ T phs[NPH];
+  __shared__ T nqs[DIM + 1][NNQ];
+
+  // Flags of the previous step's parity are cleared here, before the next
+  // step's phi kernel sets them again.
+  {
+    const unsigned nother = *cnt_other;
+    for (unsigned k = blockIdx.x * NT + threadIdx.x; k < nother; k += gridDim.x * NT)
+      flags_other[list_other[k]] = 0u;
+  }
+  const unsigned ntiles = *cnt;
+  const T q_th = (T)np.q_th, eta = (T)np.eta, cos_opp = (T)np.cos_opp, eps_n = (T)np.eps_n,
+          eps_q = (T)np.eps_q;
+  const int w = np.w;
+  const int wz = DIM == 3 ? w : 0;
+  unsigned my_active = 0;
+  for (unsigned k = blockIdx.x; k < ntiles; k += gridDim.x) {
+    const unsigned t = list[k];
+    const int tx = (int)(t % (unsigned)geo.ntx);
+    const int ty = (int)((t / (unsigned)geo.ntx) % (unsigned)geo.nty);
+    const int tz = (int)(t / ((unsigned)geo.ntx * (unsigned)geo.nty));
+    const int ox = tx * TX, oy = ty * TY, oz = tz * TZ;
+    for (int e = threadIdx.x; e < NPH; e += NT) {
+      const int ex = e % PX, ey = (e / PX) % PY, ez = e / (PX * PY);
+      const int gx = wrapi(ox + ex - PHI_HALO, geo.nx), gy = wrapi(oy + ey - PHI_HALO, geo.ny);
+      const int gz = DIM == 3 ? wrapi(oz + ez - PHI_HALO, geo.nz) : 0;
+      phs[e] = phi[gx + geo.nx * (gy + geo.ny * gz)];
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < NNQ; e += NT) {
+      const int ex = e % NX, ey = (e / NX) % NY, ez = e / (NX * NY);
+      const int c = (ex + 1) + PX * ((ey + 1) + PY * (DIM == 3 ? ez + 1 : 0));
+      T gr[3], lap;
+      grad_lap<DIM, T>([&](int i) { return phs[c + L::cx[i] + PX * (L::cy[i] + PY * L::cz[i])]; }, gr,
+                       lap);
+      T mag = gr[0] * gr[0] + gr[1] * gr[1];
+      if (DIM == 3) mag += gr[2] * gr[2];
+      mag = m_sqrt(mag);
+      const T den = mag + eps_n;
+#pragma unroll
+      for (int a = 0; a < DIM; ++a) nqs[a][e] = gr[a] / den;
+      const T ph = phs[c];
+      const T pc = ph < (T)0 ? (T)0 : (ph > (T)1 ? (T)1 : ph);
+      nqs[DIM][e] = pc * ((T)1 - pc);
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < TX * TY * TZ; e += NT) {
+      const int lx = e % TX, ly = (e / TX) % TY, lz = e / (TX * TY);
+      const int gx = ox + lx, gy = oy + ly, gz = oz + lz;
+      if (gx >= geo.nx || gy >= geo.ny || gz >= geo.nz) continue;
+      const int idx = gx + geo.nx * (gy + geo.ny * gz);
+      const int cc = (lx + NQ_HALO) + NX * ((ly + NQ_HALO) + NY * (DIM == 3 ? lz + NQ_HALO : 0));
+      const T qx = nqs[DIM][cc];
+      T Jv[3] = {0, 0, 0};
+      int found = 0, bdx = 0, bdy = 0, bdz = 0;
+      if (qx >= q_th) {
+        T nxv[3];
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) nxv[a] = nqs[a][cc];
+        const T qm = qx > eps_q ? qx : eps_q;
+        const T tol = eta * qm;
+        const T tie = (T)np.tie_eps;
+        int bd2 = 0;
+        T bdot = 0;
+        // pass 0: smallest |r|^2 among accepted candidates, and the smallest
+        // n(x).n(y) at that distance; pass 1: the first candidate in scan order
+        // at that distance whose dot lies within tie_eps of the smallest.
+        for (int pass = 0; pass < 2; ++pass) {
+          bool done = false;
+          for (int dz = -wz; dz <= wz && !done; ++dz)
+            for (int dy = -w; dy <= w && !done; ++dy)
+              for (int dx = -w; dx <= w; ++dx) {
+                if ((dx | dy | dz) == 0) continue;
+                const int d2 = dx * dx + dy * dy + dz * dz;
+                if (pass == 1 && d2 != bd2) continue;
+                const int cy_ = cc + dx + NX * (dy + NY * dz);
+                const T qy = nqs[DIM][cy_];
+                if (!(qy >= q_th)) continue;
+                if (!(m_abs(qy - qx) <= tol)) continue;
+                T dot = nxv[0] * nqs[0][cy_];
+                dot += nxv[1] * nqs[1][cy_];
+                if (DIM == 3) dot += nxv[2] * nqs[2][cy_];
+                if (!(dot <= cos_opp)) continue;
+                if (pass == 0) {
+                  if (!found || d2 < bd2 || (d2 == bd2 && dot < bdot)) {
+                    found = 1;
+                    bd2 = d2;
+                    bdot = dot;
+                  }
+                } else if (dot <= bdot + tie) {
+                  bdx = dx;
+                  bdy = dy;
+                  bdz = dz;
+                  bdot = dot;
+                  done = true;
+                  break;
+                }
+              }
+          if (!found) break;
+        }
+        if (found) {
+          const int cy_ = cc + bdx + NX * (bdy + NY * bdz);
+          const T qy = nqs[DIM][cy_];
+          T qcl = (T)0.5 * (qx + qy);
+          if (qcl < eps_q) qcl = eps_q;
+          if (qcl > (T)0.25 - eps_q) qcl = (T)0.25 - eps_q;
+          const T ff = -bdot > (T)0 ? -bdot : (T)0;
+          if (ff != (T)0) {
+            const T rn = m_sqrt((T)(bdx * bdx + bdy * bdy + bdz * bdz));
+            const T rh[3] = {(T)bdx / rn, (T)bdy / rn, (T)bdz / rn};
+            T nt[3] = {0, 0, 0}, nn = 0;
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) {
+              nt[a] = nxv[a] - nqs[a][cy_];
+              nn += nt[a] * nt[a];
+            }
+            nn = m_sqrt(nn);
+            T ns[3] = {0, 0, 0};
+            if (nn < (T)1e-6) {
+#pragma unroll
+              for (int a = 0; a < DIM; ++a) ns[a] = rh[a];
+            } else {
+#pragma unroll
+              for (int a = 0; a < DIM; ++a) ns[a] = nt[a] / (nn + eps_n);
+            }
+            T ref = 0;
+            if (np.orient == 0) {
+#pragma unroll
+              for (int a = 0; a < DIM; ++a) ref += nxv[a] * ns[a];
+            } else {
+#pragma unroll
+              for (int a = 0; a < DIM; ++a) ref += rh[a] * ns[a];
+              ref *= (T)np.orient;
+            }
+            if (ref < (T)0) {
+#pragma unroll
+              for (int a = 0; a < DIM; ++a) ns[a] = -ns[a];
+            }
+            const T h = (T)np.width * m_acosh((T)1 / ((T)2 * m_sqrt(qcl)));
+            const T wh = (T)1 / ((T)1 + m_pow(h / (T)np.h0, (T)np.p_exp));
+            const T amp = (T)np.a_rep * qcl * wh * ff;
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) Jv[a] = amp * ns[a];
+          }
+        }
+      }
+      my_active += (unsigned)found;
+#pragma unroll
+      for (int a = 0; a < DIM; ++a) J[a * geo.S + idx] = Jv[a];
+      if constexpr (DEBUG) {
+        const long long N = (long long)geo.nx * geo.ny * geo.nz;
+        chi_out[idx] = found;
+        part_out[idx] = bdx;
+        part_out[N + idx] = bdy;
+        part_out[2 * N + idx] = bdz;
+      }
+    }
+    __syncthreads();
+  }
+  my_active = wave_sum(my_active);
+  if ((threadIdx.x & 63) == 0 && my_active) atomicAdd(nci_count, my_active);
+}
+
+// ---------------------------------------------------------------------------
+// (b) fused collide + stream of both lattices (AA, in place)
+// ---------------------------------------------------------------------------
+
+enum { MODE_STEP = 0, MODE_STEP_DIAG = 1, MODE_DRY = 2 };
+
+// Block reduction of the NPART per-thread values (sums, except slot 5 = max).
+__device__ __forceinline__ void block_partials(double v[NPART], double* __restrict__ out) {
+  __shared__ double red[NT / 64][NPART];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < NPART; ++k) v[k] = (k == 5) ? wave_max(v[k]) : wave_sum(v[k]);
+  if (lane == 0)
+#pragma unroll
+    for (int k = 0; k < NPART; ++k) red[wv][k] = v[k];
+  __syncthreads();
+  if (threadIdx.x < NPART) {
+    const int k = threadIdx.x;
+    double a = red[0][k];
+    for (int j = 1; j < NT / 64; ++j) a = (k == 5) ? (red[j][k] > a ? red[j][k] : a) : a + red[j][k];
+    out[blockIdx.x * NPART + k] = a;
+  }
+}
+
+template <int DIM, int PAR, int MODE, typename T, typename FS, typename GS>
+__global__ __launch_bounds__(NT) void k_collide(FS* __restrict__ f, GS* __restrict__ g,
+                                                const T* __restrict__ phi,
+                                                const T* __restrict__ J,
+                                                const unsigned* __restrict__ flags,
+                                                unsigned* __restrict__ cnt_other, Geo geo, Phys pp,
+                                                int nci_on, int ttx, int tty, int ttz,
+                                                T* __restrict__ macro,
+                                                double* __restrict__ partials) {
+  using H = Hydro<DIM>;
+  using P = Phase<DIM>;
+  constexpr int Q = H::Q, QG = P::Q;
+  if (nci_on && blockIdx.x == 0 && threadIdx.x == 0) *cnt_other = 0u;
+  const int t = swizzled_block();
+  const int bx = t % geo.nbx, r = t / geo.nbx, by = r % geo.nby, z = r / geo.nby;
+  const int x = bx * BX + (int)(threadIdx.x & (BX - 1)), y = by * BY + (int)(threadIdx.x / BX);
+  const bool valid = x < geo.nx && y < geo.ny;
+  double acc[NPART] = {0, 0, 0, 0, 0, 0, 0, 0};
+  if (MODE == MODE_STEP && !valid) return;
+  if (valid) {
+    const Nbr nb(x, y, z, geo);
+    const int idx = nb(0, 0, 0);
+    const long long S = geo.S;
+    // ---- phase field around the cell: grad, lap, n, mu_phi
+    T gr[3], lap;
+    grad_lap<DIM, T>([&](int i) { return phi[nb(H::cx[i], H::cy[i], H::cz[i])]; }, gr, lap);
+    const T ph = phi[idx];
+    T gmag = gr[0] * gr[0] + gr[1] * gr[1];
+    if (DIM == 3) gmag += gr[2] * gr[2];
+    gmag = m_sqrt(gmag);
+    const T inv_g = (T)1 / (gmag + (T)pp.eps_n);
+    const T mu = (T)pp.beta4 * ph * (ph - (T)1) * (ph - (T)0.5) - (T)pp.kappa * lap;
+    // ---- mixture (linear rho, linear dynamic viscosity)
+    const T rho = (T)pp.rho_g + (T)pp.drho * ph;
+    const T inv_rho = (T)1 / rho;
+    const T nu = ((T)pp.mu_a + (T)pp.mu_b * ph) * inv_rho;
+    const T omega = (T)1 / ((T)0.5 + (T)3 * nu);
+    // ---- hydrodynamic populations and their moments
+    T fi[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      const int slot = PAR == 0 ? i : opp(i);
+      const int src = PAR == 0 ? idx : nb(-H::cx[i], -H::cy[i], -H::cz[i]);
+      fi[i] = Store<FS>::ld(f + slot * S + src, (T)(H::w[i] * pp.pstar_ref));
+    }
+    T ps = fi[0], m[3] = {0, 0, 0}, M2[6] = {0, 0, 0, 0, 0, 0};  // xx yy zz xy xz yz
+#pragma unroll
+    for (int i = 1; i < Q; i += 2) {
+      const T s = fi[i] + fi[i + 1], d = fi[i] - fi[i + 1];
+      ps += s;
+      const int cx = H::cx[i], cy = H::cy[i], cz = H::cz[i];
+      if (cx) m[0] += cx > 0 ? d : -d;
+      if (cy) m[1] += cy > 0 ? d : -d;
+      if (cz) m[2] += cz > 0 ? d : -d;
+      if (cx) M2[0] += s;
+      if (cy) M2[1] += s;
+      if (cz) M2[2] += s;
+      if (cx && cy) M2[3] += cx * cy > 0 ? s : -s;
+      if (cx && cz) M2[4] += cx * cz > 0 ? s : -s;
+      if (cy && cz) M2[5] += cy * cz > 0 ? s : -s;
+    }
+    // ---- forces (Eq. Fsplit): capillary, pressure correction, repulsion, buoyancy
+    T Jv[3] = {0, 0, 0};
+    if (nci_on) {
+      const unsigned tile = (unsigned)(x / ttx + geo.ntx * (y / tty + geo.nty * (z / ttz)));
+      if (flags[tile]) {
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) Jv[a] = J[a * S + idx];
+      }
+    }
+    const T cs2 = (T)(1.0 / 3.0);
+    const T drho = (T)pp.drho;
+    const T inv2rho = (T)0.5 * inv_rho;
+    T Fp[3], up[3], F[3], u[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      Fp[a] = mu * gr[a] - ps * cs2 * (drho * gr[a]) + rho * Jv[a] + (rho - (T)pp.rho_mean) * (T)pp.g[a];
+      if (a >= DIM) Fp[a] = 0;
+      up[a] = m[a] + Fp[a] * inv2rho;
+    }
+    // viscous correction (Eq. Fnu) from the second moment of f - feq(p*, u')
+    {
+      const T pc = ps * cs2;
+      const T Pxx = M2[0] - pc - up[0] * up[0], Pyy = M2[1] - pc - up[1] * up[1];
+      const T Pzz = M2[2] - pc - up[2] * up[2];
+      const T Pxy = M2[3] - up[0] * up[1], Pxz = M2[4] - up[0] * up[2], Pyz = M2[5] - up[1] * up[2];
+      const T kf = -(T)3 * nu * omega * drho;
+      F[0] = Fp[0] + kf * (Pxx * gr[0] + Pxy * gr[1] + Pxz * gr[2]);
+      F[1] = Fp[1] + kf * (Pxy * gr[0] + Pyy * gr[1] + Pyz * gr[2]);
+      F[2] = DIM == 3 ? Fp[2] + kf * (Pxz * gr[0] + Pyz * gr[1] + Pzz * gr[2]) : (T)0;
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) u[a] = m[a] + F[a] * inv2rho;
+    const T uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    const T uF = u[0] * F[0] + u[1] * F[1] + u[2] * F[2];
+    // second-order non-equilibrium moment of f - feq + S/2 (Hermite projection)
+    const T pc = ps * cs2;
+    T A[6];
+    A[0] = M2[0] - pc - u[0] * u[0] + (T)2 * u[0] * F[0] * inv2rho;
+    A[1] = M2[1] - pc - u[1] * u[1] + (T)2 * u[1] * F[1] * inv2rho;
+    A[2] = DIM == 3 ? M2[2] - pc - u[2] * u[2] + (T)2 * u[2] * F[2] * inv2rho : (T)0;
+    A[3] = M2[3] - u[0] * u[1] + (u[0] * F[1] + u[1] * F[0]) * inv2rho;
+    A[4] = DIM == 3 ? M2[4] - u[0] * u[2] + (u[0] * F[2] + u[2] * F[0]) * inv2rho : (T)0;
+    A[5] = DIM == 3 ? M2[5] - u[1] * u[2] + (u[1] * F[2] + u[2] * F[1]) * inv2rho : (T)0;
+    const T trA = A[0] + A[1] + A[2];
+    const T Au[3] = {A[0] * u[0] + A[3] * u[1] + A[4] * u[2], A[3] * u[0] + A[1] * u[1] + A[5] * u[2],
+                     A[4] * u[0] + A[5] * u[1] + A[2] * u[2]};
+    if constexpr (MODE != MODE_DRY) {
+      const T om1 = (T)1 - omega;
+      // rest population
+      {
+        const T w0 = wt<H, T>(0);
+        const T e = w0 * (ps - (T)1.5 * uu) + om1 * w0 * ((T)-1.5 * trA) + w0 * inv2rho * ((T)-3 * uF);
+        Store<FS>::st(f + 0 * S + idx, e, (T)(H::w[0] * pp.pstar_ref));
+      }
+#pragma unroll
+      for (int i = 1; i < Q; i += 2) {
+        const int cx = H::cx[i], cy = H::cy[i], cz = H::cz[i];
+        const T w = wt<H, T>(i);
+        const T cu = (T)cx * u[0] + (T)cy * u[1] + (T)cz * u[2];
+        const T cF = (T)cx * F[0] + (T)cy * F[1] + (T)cz * F[2];
+        const T cAc = (T)(cx * cx) * A[0] + (T)(cy * cy) * A[1] + (T)(cz * cz) * A[2] +
+                      (T)2 * ((T)(cx * cy) * A[3] + (T)(cx * cz) * A[4] + (T)(cy * cz) * A[5]);
+        const T cAu = (T)cx * Au[0] + (T)cy * Au[1] + (T)cz * Au[2];
+        const T cu2 = cu * cu;
+        const T ev = w * (ps + (T)4.5 * cu2 - (T)1.5 * uu) + om1 * w * ((T)4.5 * cAc - (T)1.5 * trA) +
+                     w * inv2rho * ((T)-3 * uF + (T)9 * cu * cF);
+        const T od = w * cu * ((T)3 + (T)4.5 * cu2 - (T)4.5 * uu) +
+                     om1 * w * ((T)13.5 * cu * cAc - (T)4.5 * cu * trA - (T)9 * cAu) +
+                     w * inv2rho * ((T)3 * cF);
+        const T fa = ev + od, fb = ev - od;   // directions i and opp(i)
+        if constexpr (PAR == 0) {
+          Store<FS>::st(f + (i + 1) * S + idx, fa, (T)(H::w[i] * pp.pstar_ref));
+          Store<FS>::st(f + i * S + idx, fb, (T)(H::w[i] * pp.pstar_ref));
+        } else {
+          Store<FS>::st(f + i * S + nb(cx, cy, cz), fa, (T)(H::w[i] * pp.pstar_ref));
+          Store<FS>::st(f + (i + 1) * S + nb(-cx, -cy, -cz), fb, (T)(H::w[i] * pp.pstar_ref));
+        }
+      }
+      // ---- conservative Allen-Cahn populations: BGK towards
+      //      geq_k = w_k (phi + c_k . j / cs_phi^2), j = phi u + M (4/W) phi (1-phi) n
+      const T kc = (T)pp.kc * ph * ((T)1 - ph) * inv_g;
+      const T jv[3] = {ph * u[0] + kc * gr[0], ph * u[1] + kc * gr[1], ph * u[2] + kc * gr[2]};
+      const T itp = (T)pp.inv_tau_phi;
+      GS* gp = g;
+      T gi[QG];
+#pragma unroll
+      for (int k = 0; k < QG; ++k) {
+        const int slot = PAR == 0 ? k : opp(k);
+        const int src = PAR == 0 ? idx : nb(-P::cx[k], -P::cy[k], -P::cz[k]);
+        gi[k] = (T)gp[slot * S + src];
+      }
+      {
+        const T geq = wt<P, T>(0) * ph;
+        gp[0 * S + idx] = (GS)(gi[0] - (gi[0] - geq) * itp);
+      }
+#pragma unroll
+      for (int k = 1; k < QG; k += 2) {
+        const int cx = P::cx[k], cy = P::cy[k], cz = P::cz[k];
+        const T cj = ((T)cx * jv[0] + (T)cy * jv[1] + (T)cz * jv[2]) * (T)P::inv_cs2;
+        const T wk = wt<P, T>(k);
+        const T ga = gi[k] - (gi[k] - wk * (ph + cj)) * itp;
+        const T gb = gi[k + 1] - (gi[k + 1] - wk * (ph - cj)) * itp;
+        if constexpr (PAR == 0) {
+          gp[(k + 1) * S + idx] = (GS)ga;
+          gp[k * S + idx] = (GS)gb;
+        } else {
+          gp[k * S + nb(cx, cy, cz)] = (GS)ga;
+          gp[(k + 1) * S + nb(-cx, -cy, -cz)] = (GS)gb;
+        }
+      }
+    } else if (macro) {
+      // dry evaluation: macroscopic fields of the current state
+      macro[0 * S + idx] = ps;
+      macro[1 * S + idx] = rho;
+#pragma unroll
+      for (int a = 0; a < DIM; ++a) {
+        macro[(2 + a) * S + idx] = u[a];
+        macro[(2 + DIM + a) * S + idx] = F[a];
+      }
+    }
+    if constexpr (MODE != MODE_STEP) {
+      const double dr = (double)rho;
+      acc[0] = (double)ps;
+      acc[1] = dr * (double)u[0];
+      acc[2] = dr * (double)u[1];
+      acc[3] = dr * (double)u[2];
+      const double sp2 = (double)u[0] * (double)u[0] + (double)u[1] * (double)u[1] + (double)u[2] * (double)u[2];
+      acc[4] = 0.5 * dr * sp2;
+      acc[5] = sqrt(sp2);
+      const bool fin = isfinite((double)ps) && isfinite(sp2);
+      acc[6] = fin ? 0.0 : 1.0;
+      if (!fin) acc[5] = 0.0;
+    }
+  }
+  if constexpr (MODE != MODE_STEP) block_partials(acc, partials);
+}
+
+// ---------------------------------------------------------------------------
+// (c) diagnostics: sum phi and the Euler characteristic of the dispersed set
+// ---------------------------------------------------------------------------
+
+// Euler characteristic of the union of closed voxels {fg}: each cell owns the
+// vertex at its (+1/2,+1/2,+1/2) corner, the three edges ending there from the
+// -x, -y, -z sides, the three faces on its +x, +y, +z sides and its own voxel.
+template <int DIM, typename T>
+__global__ __launch_bounds__(NT) void k_diag(const T* __restrict__ phi, Geo geo, int dispersed,
+                                             double* __restrict__ partials) {
+  const int t = swizzled_block();
+  const int bx = t % geo.nbx, r = t / geo.nbx, by = r % geo.nby, z = r / geo.nby;
+  const int x = bx * BX + (int)(threadIdx.x & (BX - 1)), y = by * BY + (int)(threadIdx.x / BX);
+  double acc[NPART] = {0, 0, 0, 0, 0, 0, 0, 0};
+  if (x < geo.nx && y < geo.ny) {
+    const Nbr nb(x, y, z, geo);
+    auto fg = [&](int dx, int dy, int dz) -> int {
+      const T v = phi[nb(dx, dy, dz)];
+      return dispersed ? (v > (T)0.5) : (v < (T)0.5);
+    };
+    const T p0 = phi[nb(0, 0, 0)];
+    acc[0] = (double)p0;
+    acc[6] = isfinite((double)p0) ? 0.0 : 1.0;
+    int chi;
+    if (DIM == 2) {
+      const int b00 = fg(0, 0, 0), b10 = fg(1, 0, 0), b01 = fg(0, 1, 0), b11 = fg(1, 1, 0);
+      chi = (b00 | b10 | b01 | b11) - (b00 | b01) - (b00 | b10) + b00;
+    } else {
+      const int b000 = fg(0, 0, 0), b100 = fg(1, 0, 0), b010 = fg(0, 1, 0), b001 = fg(0, 0, 1);
+      const int b110 = fg(1, 1, 0), b101 = fg(1, 0, 1), b011 = fg(0, 1, 1), b111 = fg(1, 1, 1);
+      const int V = b000 | b100 | b010 | b001 | b110 | b101 | b011 | b111;
+      const int Ex = b000 | b010 | b001 | b011;
+      const int Ey = b000 | b100 | b001 | b101;
+      const int Ez = b000 | b100 | b010 | b110;
+      const int Fx = b000 | b100, Fy = b000 | b010, Fz = b000 | b001;
+      chi = V - (Ex + Ey + Ez) + (Fx + Fy + Fz) - b000;
+    }
+    acc[1] = (double)chi;
+  }
+  block_partials(acc, partials);
+}
+
+// Deterministic final reduction of per-block partials: out[0..7] for the
+// collide partials, out[8..15] for the diag partials.
+__global__ __launch_bounds__(NT) void k_reduce(const double* __restrict__ pa, int na,
+                                               const double* __restrict__ pb, int nb_,
+                                               const unsigned* __restrict__ nci_count,
+                                               double* __restrict__ out) {
+  __shared__ double red[NT][NPART];
+  for (int pass = 0; pass < 2; ++pass) {
+    const double* p = pass ? pb : pa;
+    const int n = pass ? nb_ : na;
+    double v[NPART] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int b = threadIdx.x; b < n; b += NT)
+      for (int k = 0; k < NPART; ++k) v[k] = (k == 5) ? fmax(v[k], p[b * NPART + k]) : v[k] + p[b * NPART + k];
+    for (int k = 0; k < NPART; ++k) red[threadIdx.x][k] = v[k];
+    __syncthreads();
+    for (int s = NT / 2; s > 0; s >>= 1) {
+      if ((int)threadIdx.x < s)
+        for (int k = 0; k < NPART; ++k)
+          red[threadIdx.x][k] = (k == 5) ? fmax(red[threadIdx.x][k], red[threadIdx.x + s][k])
+                                         : red[threadIdx.x][k] + red[threadIdx.x + s][k];
+      __syncthreads();
+    }
+    if (threadIdx.x < NPART) out[pass * NPART + threadIdx.x] = red[0][threadIdx.x];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[7] = nci_count ? (double)*nci_count : 0.0;
+}
+
+// ---------------------------------------------------------------------------
+// initial populations, population I/O
+// ---------------------------------------------------------------------------
+
+// f = feq(p*, u) (Eq. feq3), g = geq(phi, u, n) in natural layout (parity 0).
+template <int DIM, typename T, typename FS, typename GS>
+__global__ __launch_bounds__(NT) void k_init(FS* __restrict__ f, GS* __restrict__ g,
+                                             const T* __restrict__ phi, const T* __restrict__ uin,
+                                             const T* __restrict__ psin, Geo geo, Phys pp) {
+  using H = Hydro<DIM>;
+  using P = Phase<DIM>;
+  const int t = swizzled_block();
+  const int bx = t % geo.nbx, r = t / geo.nbx, by = r % geo.nby, z = r / geo.nby;
+  const int x = bx * BX + (int)(threadIdx.x & (BX - 1)), y = by * BY + (int)(threadIdx.x / BX);
+  if (x >= geo.nx || y >= geo.ny) return;
+  const Nbr nb(x, y, z, geo);
+  const int idx = nb(0, 0, 0);
+  const long long S = geo.S;
+  T u[3] = {0, 0, 0};
+#pragma unroll
+  for (int a = 0; a < DIM; ++a) u[a] = uin[a * S + idx];
+  const T ps = psin[idx];
+  const T uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+#pragma unroll
+  for (int i = 0; i < H::Q; ++i) {
+    const T cu = (T)H::cx[i] * u[0] + (T)H::cy[i] * u[1] + (T)H::cz[i] * u[2];
+    const T fe = wt<H, T>(i) * (ps + (T)3 * cu + (T)4.5 * cu * cu - (T)1.5 * uu + (T)4.5 * cu * cu * cu -
+                               (T)4.5 * cu * uu);
+    Store<FS>::st(f + i * S + idx, fe, (T)(H::w[i] * pp.pstar_ref));
+  }
+  T gr[3], lap;
+  grad_lap<DIM, T>([&](int i) { return phi[nb(H::cx[i], H::cy[i], H::cz[i])]; }, gr, lap);
+  const T ph = phi[idx];
+  T gmag = m_sqrt(gr[0] * gr[0] + gr[1] * gr[1] + gr[2] * gr[2]);
+  const T kc = (T)pp.kc * ph * ((T)1 - ph) / (gmag + (T)pp.eps_n);
+#pragma unroll
+  for (int k = 0; k < P::Q; ++k) {
+    const T cj = (T)P::cx[k] * (ph * u[0] + kc * gr[0]) + (T)P::cy[k] * (ph * u[1] + kc * gr[1]) +
+                 (T)P::cz[k] * (ph * u[2] + kc * gr[2]);
+    g[k * S + idx] = (GS)(wt<P, T>(k) * (ph + cj * (T)P::inv_cs2));
+  }
+}
+
+// Incoming populations on a wrapped box, as doubles, SoA [q][box].
+template <int DIM, int PAR, typename T, typename FS, typename GS>
+__global__ __launch_bounds__(NT) void k_getpop(const FS* __restrict__ f, const GS* __restrict__ g,
+                                               Geo geo, Phys pp, int x0, int y0, int z0, int bxn,
+                                               int byn, int bzn, double* __restrict__ fo,
+                                               double* __restrict__ go) {
+  using H = Hydro<DIM>;
+  using P = Phase<DIM>;
+  const long long B = (long long)bxn * byn * bzn;
+  const long long e = (long long)blockIdx.x * NT + threadIdx.x;
+  if (e >= B) return;
+  const int lx = (int)(e % bxn), ly = (int)((e / bxn) % byn), lz = (int)(e / ((long long)bxn * byn));
+  const int x = wrapi(x0 + lx, geo.nx), y = wrapi(y0 + ly, geo.ny), z = wrapi(z0 + lz, geo.nz);
+  const Nbr nb(x, y, z, geo);
+  const int idx = nb(0, 0, 0);
+  for (int i = 0; i < H::Q; ++i) {
+    const int slot = PAR == 0 ? i : opp(i);
+    const int src = PAR == 0 ? idx : nb(-H::cx[i], -H::cy[i], -H::cz[i]);
+    fo[i * B + e] = (double)Store<FS>::ld(f + slot * geo.S + src, (T)(H::w[i] * pp.pstar_ref));
+  }
+  for (int k = 0; k < P::Q; ++k) {
+    const int slot = PAR == 0 ? k : opp(k);
+    const int src = PAR == 0 ? idx : nb(-P::cx[k], -P::cy[k], -P::cz[k]);
+    go[k * B + e] = (double)g[slot * geo.S + src];
+  }
+}
+
+// Whole-field populations (doubles, SoA [q][N]) into natural layout.
+template <int DIM, typename T, typename FS, typename GS>
+__global__ __launch_bounds__(NT) void k_setpop(FS* __restrict__ f, GS* __restrict__ g, Geo geo,
+                                               Phys pp, const double* __restrict__ fi,
+                                               const double* __restrict__ gi) {
+  using H = Hydro<DIM>;
+  using P = Phase<DIM>;
+  const long long N = (long long)geo.nx * geo.ny * geo.nz;
+  const long long e = (long long)blockIdx.x * NT + threadIdx.x;
+  if (e >= N) return;
+  for (int i = 0; i < H::Q; ++i)
+    Store<FS>::st(f + i * geo.S + e, (T)fi[i * N + e], (T)(H::w[i] * pp.pstar_ref));
+  for (int k = 0; k < P::Q; ++k) g[k * geo.S + e] = (GS)gi[k * N + e];
+}
+
+}  // namespace lbm

@@ -1,0 +1,870 @@
+// lbm.hip -- host side of the C ABI declared in include/lbm.h.
+//
+// A context owns (or borrows) one device workspace that holds everything the
+// step keeps resident: the two population arrays (AA, structure-of-arrays),
+// phi, the repulsive flux J, the near-contact tile flags and lists, and the
+// reduction scratch.  Each step enqueues k_phi, k_nci (when A_rep != 0) and
+// k_collide on the context's stream; every diag_interval steps the collide
+// kernel also produces FP64 partial sums and k_diag / k_reduce finish them.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/lbm.h"
+#include "kernels.hpp"
+
+using namespace lbm;
+
+namespace {
+
+constexpr int HIST = 64;      // periodic diagnostics kept on the device
+constexpr int NCI_GRID = 2048;
+
+thread_local std::string g_create_error;
+
+size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+int q_hydro(int dim) { return dim == 2 ? 9 : 19; }
+int q_phase(int dim) { return dim == 2 ? 9 : 7; }
+
+size_t real_size(int prec) { return prec == LBM_FP64 ? 8 : 4; }
+size_t fstore_size(int prec) { return prec == LBM_FP64 ? 8 : (prec == LBM_FP32 ? 4 : 2); }
+
+void tile_dims(int dim, int prec, int* tx, int* ty, int* tz) {
+  if (dim == 2) {
+    *tx = 16; *ty = 16; *tz = 1;
+  } else if (prec == LBM_FP64) {
+    *tx = 8; *ty = 8; *tz = 4;
+  } else {
+    *tx = 8; *ty = 8; *tz = 8;
+  }
+}
+
+struct Layout {
+  long long N, S;
+  int nblk, ntiles, ttx, tty, ttz, ntx, nty, ntz;
+  size_t off_f, off_g, off_phi, off_J, off_flags, off_list, off_cnt, off_pa, off_pb, off_red,
+      total;
+};
+
+bool valid_params(const lbm_params* p, std::string* why) {
+  auto bad = [&](const char* m) {
+    if (why) *why = m;
+    return false;
+  };
+  if (!p) return bad("null parameters");
+  if (p->dim != 2 && p->dim != 3) return bad("dim must be 2 or 3");
+  if (p->nx < 1 || p->ny < 1 || p->nz < 1) return bad("box sizes must be positive");
+  if (p->dim == 2 && p->nz != 1) return bad("2D boxes need nz = 1");
+  const long long N = (long long)p->nx * p->ny * p->nz;
+  if (N >= (1LL << 31) - 4096) return bad("box too large (more than 2^31 cells)");
+  if (p->precision < LBM_FP64 || p->precision > LBM_FP32_BF16STORE) return bad("unknown precision");
+  if (!(p->tau > 0.5)) return bad("tau must exceed 1/2");
+  if (!(p->visc_ratio > 0)) return bad("visc_ratio must be positive");
+  if (!(p->mobility > 0)) return bad("mobility must be positive");
+  if (!(p->width > 0)) return bad("width must be positive");
+  if (!(p->sigma >= 0)) return bad("sigma must be non-negative");
+  if (!(p->density_ratio > 0)) return bad("density_ratio must be positive");
+  if (!(p->a_rep >= 0)) return bad("a_rep must be non-negative");
+  if (p->nci_window < 1 || p->nci_window > 3) return bad("nci_window must be 1, 2 or 3");
+  if (!(p->h0 > 0) || !(p->p_exp > 0)) return bad("h0 and p_exp must be positive");
+  if (!(p->eps_q >= 0) || !(p->eps_q < 0.125) || !(p->eps_n >= 0)) return bad("bad eps_q / eps_n");
+  if (!(p->tie_eps >= 0) || !(p->tie_eps < 0.1)) return bad("tie_eps must be in [0, 0.1)");
+  if (p->rep_orient < -1 || p->rep_orient > 1) return bad("rep_orient must be -1, 0 or 1");
+  if (p->dispersed < -1 || p->dispersed > 1) return bad("dispersed must be -1, 0 or 1");
+  if (p->diag_interval < 0) return bad("diag_interval must be >= 0");
+  return true;
+}
+
+Layout make_layout(const lbm_params* p) {
+  Layout L{};
+  L.N = (long long)p->nx * p->ny * p->nz;
+  L.S = (L.N + 127) & ~127LL;
+  const int nbx = (p->nx + BX - 1) / BX, nby = (p->ny + BY - 1) / BY;
+  L.nblk = nbx * nby * p->nz;
+  tile_dims(p->dim, p->precision, &L.ttx, &L.tty, &L.ttz);
+  L.ntx = (p->nx + L.ttx - 1) / L.ttx;
+  L.nty = (p->ny + L.tty - 1) / L.tty;
+  L.ntz = (p->nz + L.ttz - 1) / L.ttz;
+  L.ntiles = L.ntx * L.nty * L.ntz;
+  const size_t rs = real_size(p->precision), fs = fstore_size(p->precision);
+  size_t o = 0;
+  L.off_f = o;   o = align256(o + (size_t)q_hydro(p->dim) * L.S * fs);
+  L.off_g = o;   o = align256(o + (size_t)q_phase(p->dim) * L.S * rs);
+  L.off_phi = o; o = align256(o + (size_t)L.S * rs);
+  L.off_J = o;   o = align256(o + (size_t)p->dim * L.S * rs);
+  L.off_flags = o; o = align256(o + 2 * (size_t)L.ntiles * 4);
+  L.off_list = o;  o = align256(o + 2 * (size_t)L.ntiles * 4);
+  L.off_cnt = o;   o = align256(o + 64);
+  L.off_pa = o;    o = align256(o + (size_t)L.nblk * NPART * 8);
+  L.off_pb = o;    o = align256(o + (size_t)L.nblk * NPART * 8);
+  L.off_red = o;   o = align256(o + (size_t)(HIST + 1) * 2 * NPART * 8);
+  L.total = o;
+  return L;
+}
+
+}  // namespace
+
+struct lbm_ctx {
+  lbm_params p;
+  Layout L;
+  int dev = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  char* ws = nullptr;
+  bool own_ws = false;
+  Geo geo{};
+  Phys phys{};
+  NciP nci{};
+  long step = 0;
+  bool initialised = false;
+  int dispersed = 1;
+  long hist_step[HIST];
+  int hist_count = 0;   // diagnostics recorded since the last reset
+  std::string err;
+  // per-kernel event timing
+  bool timing = false;
+  std::vector<hipEvent_t> ev;      // pairs (start, stop)
+  std::vector<int> ev_kind;
+  int ev_used = 0;
+  double k_ms[4] = {0, 0, 0, 0};
+  long k_cnt[4] = {0, 0, 0, 0};
+
+  void* f() const { return ws + L.off_f; }
+  void* g() const { return ws + L.off_g; }
+  void* phi() const { return ws + L.off_phi; }
+  void* J() const { return ws + L.off_J; }
+  unsigned* flags(int k) const { return (unsigned*)(ws + L.off_flags) + (size_t)k * L.ntiles; }
+  unsigned* list(int k) const { return (unsigned*)(ws + L.off_list) + (size_t)k * L.ntiles; }
+  unsigned* cnt() const { return (unsigned*)(ws + L.off_cnt); }   // [0],[1] lists, [2] chi count
+  double* pa() const { return (double*)(ws + L.off_pa); }
+  double* pb() const { return (double*)(ws + L.off_pb); }
+  double* red(int slot) const { return (double*)(ws + L.off_red) + (size_t)slot * 2 * NPART; }
+  bool nci_on() const { return p.a_rep > 0.0; }
+  int fail(int code, const std::string& m) {
+    err = m;
+    return code;
+  }
+};
+
+#define HIP_OR_FAIL(ctx, expr)                                                             \
+  do {                                                                                     \
+    hipError_t e_ = (expr);                                                                \
+    if (e_ != hipSuccess) return (ctx)->fail(LBM_E_HIP, std::string(#expr ": ") + hipGetErrorString(e_)); \
+  } while (0)
+
+namespace {
+
+constexpr int EV_PAIRS = 2048;
+
+int flush_timing(lbm_ctx* c) {
+  if (c->ev_used == 0) return LBM_OK;
+  HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+  for (int k = 0; k < c->ev_used; ++k) {
+    float ms = 0.f;
+    HIP_OR_FAIL(c, hipEventElapsedTime(&ms, c->ev[2 * k], c->ev[2 * k + 1]));
+    c->k_ms[c->ev_kind[k]] += ms;
+    c->k_cnt[c->ev_kind[k]] += 1;
+  }
+  c->ev_used = 0;
+  return LBM_OK;
+}
+
+// Brackets one launch with a pair of events when timing is on.
+struct Timed {
+  lbm_ctx* c;
+  int slot = -1;
+  Timed(lbm_ctx* c_, int kind) : c(c_) {
+    if (!c->timing) return;
+    if (c->ev_used == EV_PAIRS) flush_timing(c);
+    slot = c->ev_used++;
+    c->ev_kind[slot] = kind;
+    (void)hipEventRecord(c->ev[2 * slot], c->stream);
+  }
+  ~Timed() {
+    if (slot >= 0) (void)hipEventRecord(c->ev[2 * slot + 1], c->stream);
+  }
+};
+
+// ---------------------------------------------------------------------------
+// Typed launch sequences
+// ---------------------------------------------------------------------------
+
+template <typename T>
+int copy_field_to_host(lbm_ctx* c, const T* dsrc, long long comps, double* out) {
+  const long long N = c->L.N, S = c->L.S;
+  std::vector<T> h((size_t)comps * S);
+  HIP_OR_FAIL(c, hipMemcpyAsync(h.data(), dsrc, sizeof(T) * comps * S, hipMemcpyDeviceToHost, c->stream));
+  HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+  for (long long a = 0; a < comps; ++a)
+    for (long long i = 0; i < N; ++i) out[a * N + i] = (double)h[(size_t)(a * S + i)];
+  return LBM_OK;
+}
+
+void fill_diag(const double* r, long step, lbm_diag* d) {
+  std::memset(d, 0, sizeof(*d));
+  d->step = step;
+  d->sum_pstar = r[0];
+  d->momentum[0] = r[1];
+  d->momentum[1] = r[2];
+  d->momentum[2] = r[3];
+  d->kinetic_energy = r[4];
+  d->max_speed = r[5];
+  d->nci_active = (long)r[7];
+  d->mass_phi = r[NPART + 0];
+  d->n_droplets = (long)std::llround(r[NPART + 1]);
+  d->finite = (r[6] == 0.0 && r[NPART + 6] == 0.0 && std::isfinite(r[NPART + 0])) ? 1 : 0;
+}
+
+template <int DIM, typename T, typename FS, typename GS>
+struct Engine {
+  static dim3 rows(const lbm_ctx* c) { return dim3((unsigned)c->L.nblk); }
+
+  // phi of the current state, plus (when the near-contact force is on) the
+  // interfacial tile list of this parity.
+  static void phi_pass(lbm_ctx* c, int par) {
+    const int nci = c->nci_on() ? 1 : 0;
+    auto k = par == 0 ? k_phi<DIM, 0, T, GS> : k_phi<DIM, 1, T, GS>;
+    Timed tm(c, 0);
+    hipLaunchKernelGGL(k, rows(c), dim3(NT), 0, c->stream, (const GS*)c->g(), (T*)c->phi(), c->geo,
+                       c->flags(par), c->list(par), c->cnt() + par, c->cnt() + 2, nci,
+                       (T)c->p.q_th, c->L.ttx, c->L.tty, c->L.ttz);
+  }
+
+  static void nci_pass(lbm_ctx* c, int par, int* chi, int* part) {
+    if (!c->nci_on()) return;
+    const int grid = std::min(NCI_GRID, std::max(1, c->L.ntiles));
+    Timed tm(c, 1);
+    if (chi) {
+      hipLaunchKernelGGL((k_nci<DIM, T, true>), dim3(grid), dim3(NT), 0, c->stream,
+                         (const T*)c->phi(), (T*)c->J(), chi, part, c->list(par), c->cnt() + par,
+                         c->flags(1 - par), c->list(1 - par), c->cnt() + (1 - par), c->cnt() + 2,
+                         c->geo, c->nci);
+    } else {
+      hipLaunchKernelGGL((k_nci<DIM, T, false>), dim3(grid), dim3(NT), 0, c->stream,
+                         (const T*)c->phi(), (T*)c->J(), (int*)nullptr, (int*)nullptr, c->list(par),
+                         c->cnt() + par, c->flags(1 - par), c->list(1 - par), c->cnt() + (1 - par),
+                         c->cnt() + 2, c->geo, c->nci);
+    }
+  }
+
+  template <int MODE>
+  static void collide_pass(lbm_ctx* c, int par, T* macro) {
+    auto k = par == 0 ? k_collide<DIM, 0, MODE, T, FS, GS> : k_collide<DIM, 1, MODE, T, FS, GS>;
+    Timed tm(c, 2);
+    hipLaunchKernelGGL(k, rows(c), dim3(NT), 0, c->stream, (FS*)c->f(), (GS*)c->g(),
+                       (const T*)c->phi(), (const T*)c->J(), (const unsigned*)c->flags(par),
+                       c->cnt() + (1 - par), c->geo, c->phys, c->nci_on() ? 1 : 0, c->L.ttx,
+                       c->L.tty, c->L.ttz, macro, c->pa());
+  }
+
+  static void diag_finish(lbm_ctx* c, int slot) {
+    Timed tm(c, 3);
+    hipLaunchKernelGGL((k_diag<DIM, T>), rows(c), dim3(NT), 0, c->stream, (const T*)c->phi(), c->geo,
+                       c->dispersed, c->pb());
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(NT), 0, c->stream, (const double*)c->pa(), c->L.nblk,
+                       (const double*)c->pb(), c->L.nblk,
+                       (const unsigned*)(c->nci_on() ? c->cnt() + 2 : nullptr), c->red(slot));
+  }
+
+  static int step(lbm_ctx* c, int n) {
+    const int K = c->p.diag_interval;
+    for (int s = 0; s < n; ++s) {
+      const int par = (int)(c->step & 1);
+      phi_pass(c, par);
+      nci_pass(c, par, nullptr, nullptr);
+      const bool diag = K > 0 && (c->step % K) == 0;
+      if (diag) {
+        collide_pass<MODE_STEP_DIAG>(c, par, nullptr);
+        const int slot = 1 + (c->hist_count % HIST);
+        diag_finish(c, slot);
+        c->hist_step[c->hist_count % HIST] = c->step;
+        c->hist_count++;
+      } else {
+        collide_pass<MODE_STEP>(c, par, nullptr);
+      }
+      c->step++;
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return c->fail(LBM_E_HIP, std::string("launch: ") + hipGetErrorString(e));
+    return LBM_OK;
+  }
+
+  // Evaluate the current state without advancing it.  macro (device, may be
+  // null) receives p*, rho, u, F; the reduction lands in red(0).
+  static int evaluate(lbm_ctx* c, T* macro, int* chi, int* part) {
+    const int par = (int)(c->step & 1);
+    phi_pass(c, par);
+    nci_pass(c, par, chi, part);
+    collide_pass<MODE_DRY>(c, par, macro);
+    diag_finish(c, 0);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return c->fail(LBM_E_HIP, std::string("launch: ") + hipGetErrorString(e));
+    return LBM_OK;
+  }
+
+  static int init(lbm_ctx* c, const double* phi, const double* u, const double* ps) {
+    const long long N = c->L.N, S = c->L.S;
+    std::vector<T> hphi(N), hu((size_t)DIM * S, (T)0), hps(N);
+    for (long long i = 0; i < N; ++i) {
+      hphi[i] = (T)phi[i];
+      hps[i] = (T)(ps ? ps[i] : c->p.pstar_ref);
+      if (u)
+        for (int a = 0; a < DIM; ++a) hu[(size_t)a * S + i] = (T)u[(size_t)a * N + i];
+    }
+    T *du = nullptr, *dps = nullptr;
+    HIP_OR_FAIL(c, hipMalloc(&du, sizeof(T) * DIM * S));
+    if (hipMalloc(&dps, sizeof(T) * S) != hipSuccess) {
+      (void)hipFree(du);
+      return c->fail(LBM_E_OOM, "temporary allocation failed");
+    }
+    int rc = LBM_OK;
+    do {
+      if (hipMemcpyAsync(c->phi(), hphi.data(), sizeof(T) * N, hipMemcpyHostToDevice, c->stream) ||
+          hipMemcpyAsync(du, hu.data(), sizeof(T) * DIM * S, hipMemcpyHostToDevice, c->stream) ||
+          hipMemcpyAsync(dps, hps.data(), sizeof(T) * N, hipMemcpyHostToDevice, c->stream)) {
+        rc = c->fail(LBM_E_HIP, "host to device copy failed");
+        break;
+      }
+      hipLaunchKernelGGL((k_init<DIM, T, FS, GS>), rows(c), dim3(NT), 0, c->stream, (FS*)c->f(),
+                         (GS*)c->g(), (const T*)c->phi(), (const T*)du, (const T*)dps, c->geo, c->phys);
+      if (hipGetLastError() != hipSuccess || hipStreamSynchronize(c->stream) != hipSuccess)
+        rc = c->fail(LBM_E_HIP, "initialisation kernel failed");
+    } while (0);
+    (void)hipFree(du);
+    (void)hipFree(dps);
+    return rc;
+  }
+
+  static int get_pop(lbm_ctx* c, int x0, int y0, int z0, int bx, int by, int bz, double* fo,
+                     double* go) {
+    const long long B = (long long)bx * by * bz;
+    double *df = nullptr, *dg = nullptr;
+    HIP_OR_FAIL(c, hipMalloc(&df, sizeof(double) * Hydro<DIM>::Q * B));
+    if (hipMalloc(&dg, sizeof(double) * Phase<DIM>::Q * B) != hipSuccess) {
+      (void)hipFree(df);
+      return c->fail(LBM_E_OOM, "temporary allocation failed");
+    }
+    const int par = (int)(c->step & 1);
+    auto k = par == 0 ? k_getpop<DIM, 0, T, FS, GS> : k_getpop<DIM, 1, T, FS, GS>;
+    hipLaunchKernelGGL(k, dim3((unsigned)((B + NT - 1) / NT)), dim3(NT), 0, c->stream,
+                       (const FS*)c->f(), (const GS*)c->g(), c->geo, c->phys, x0, y0, z0, bx, by, bz,
+                       df, dg);
+    int rc = LBM_OK;
+    if (hipStreamSynchronize(c->stream) != hipSuccess ||
+        (fo && hipMemcpy(fo, df, sizeof(double) * Hydro<DIM>::Q * B, hipMemcpyDeviceToHost)) ||
+        (go && hipMemcpy(go, dg, sizeof(double) * Phase<DIM>::Q * B, hipMemcpyDeviceToHost)))
+      rc = c->fail(LBM_E_HIP, "population read-back failed");
+    (void)hipFree(df);
+    (void)hipFree(dg);
+    return rc;
+  }
+
+  static int set_pop(lbm_ctx* c, const double* fi, const double* gi) {
+    const long long N = c->L.N;
+    double *df = nullptr, *dg = nullptr;
+    HIP_OR_FAIL(c, hipMalloc(&df, sizeof(double) * Hydro<DIM>::Q * N));
+    if (hipMalloc(&dg, sizeof(double) * Phase<DIM>::Q * N) != hipSuccess) {
+      (void)hipFree(df);
+      return c->fail(LBM_E_OOM, "temporary allocation failed");
+    }
+    int rc = LBM_OK;
+    if (hipMemcpy(df, fi, sizeof(double) * Hydro<DIM>::Q * N, hipMemcpyHostToDevice) ||
+        hipMemcpy(dg, gi, sizeof(double) * Phase<DIM>::Q * N, hipMemcpyHostToDevice)) {
+      rc = c->fail(LBM_E_HIP, "host to device copy failed");
+    } else {
+      hipLaunchKernelGGL((k_setpop<DIM, T, FS, GS>), dim3((unsigned)((N + NT - 1) / NT)), dim3(NT), 0,
+                         c->stream, (FS*)c->f(), (GS*)c->g(), c->geo, c->phys, df, dg);
+      if (hipStreamSynchronize(c->stream) != hipSuccess) rc = c->fail(LBM_E_HIP, "set kernel failed");
+    }
+    (void)hipFree(df);
+    (void)hipFree(dg);
+    return rc;
+  }
+
+  // which: 0 p*, 1 rho, 2 u, 3 F
+  static int get_macro(lbm_ctx* c, int which, double* out) {
+    T* macro = nullptr;
+    const long long S = c->L.S;
+    HIP_OR_FAIL(c, hipMalloc(&macro, sizeof(T) * (2 + 2 * DIM) * S));
+    int rc = evaluate(c, macro, nullptr, nullptr);
+    if (rc == LBM_OK) {
+      const long long first = which == 0 ? 0 : (which == 1 ? 1 : (which == 2 ? 2 : 2 + DIM));
+      const long long comps = which <= 1 ? 1 : DIM;
+      rc = copy_field_to_host<T>(c, macro + first * S, comps, out);
+    }
+    (void)hipFree(macro);
+    return rc;
+  }
+
+  static int get_phi(lbm_ctx* c, double* out) {
+    const int par = (int)(c->step & 1);
+    phi_pass(c, par);
+    return copy_field_to_host<T>(c, (const T*)c->phi(), 1, out);
+  }
+
+  static int get_nci(lbm_ctx* c, int* chi, int* part, double* J) {
+    const long long N = c->L.N;
+    int *dchi = nullptr, *dpart = nullptr;
+    HIP_OR_FAIL(c, hipMalloc(&dchi, sizeof(int) * N));
+    if (hipMalloc(&dpart, sizeof(int) * 3 * N) != hipSuccess) {
+      (void)hipFree(dchi);
+      return c->fail(LBM_E_OOM, "temporary allocation failed");
+    }
+    int rc = LBM_OK;
+    (void)hipMemsetAsync(dchi, 0, sizeof(int) * N, c->stream);
+    (void)hipMemsetAsync(dpart, 0, sizeof(int) * 3 * N, c->stream);
+    (void)hipMemsetAsync(c->J(), 0, sizeof(T) * DIM * c->L.S, c->stream);
+    const int par = (int)(c->step & 1);
+    phi_pass(c, par);
+    nci_pass(c, par, dchi, dpart);
+    if (hipStreamSynchronize(c->stream) != hipSuccess) rc = c->fail(LBM_E_HIP, "near-contact pass failed");
+    if (rc == LBM_OK && chi && hipMemcpy(chi, dchi, sizeof(int) * N, hipMemcpyDeviceToHost)) rc = LBM_E_HIP;
+    if (rc == LBM_OK && part && hipMemcpy(part, dpart, sizeof(int) * 3 * N, hipMemcpyDeviceToHost)) rc = LBM_E_HIP;
+    if (rc == LBM_OK && J) rc = copy_field_to_host<T>(c, (const T*)c->J(), DIM, J);
+    (void)hipFree(dchi);
+    (void)hipFree(dpart);
+    return rc;
+  }
+
+  static int diagnostics(lbm_ctx* c, lbm_diag* out) {
+    int rc = evaluate(c, nullptr, nullptr, nullptr);
+    if (rc != LBM_OK) return rc;
+    double r[2 * NPART];
+    HIP_OR_FAIL(c, hipMemcpyAsync(r, c->red(0), sizeof(r), hipMemcpyDeviceToHost, c->stream));
+    HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+    fill_diag(r, c->step, out);
+    return LBM_OK;
+  }
+};
+
+// Dispatch a functor over the (dimension, precision) combinations that are built.
+template <typename Fn>
+int dispatch(const lbm_ctx* c, Fn&& fn) {
+  const int d = c->p.dim, pr = c->p.precision;
+  if (d == 2 && pr == LBM_FP64) return fn(Engine<2, double, double, double>{});
+  if (d == 2 && pr == LBM_FP32) return fn(Engine<2, float, float, float>{});
+  if (d == 2 && pr == LBM_FP32_F16STORE) return fn(Engine<2, float, __half, float>{});
+  if (d == 2 && pr == LBM_FP32_BF16STORE) return fn(Engine<2, float, __hip_bfloat16, float>{});
+  if (d == 3 && pr == LBM_FP64) return fn(Engine<3, double, double, double>{});
+  if (d == 3 && pr == LBM_FP32) return fn(Engine<3, float, float, float>{});
+  if (d == 3 && pr == LBM_FP32_F16STORE) return fn(Engine<3, float, __half, float>{});
+  if (d == 3 && pr == LBM_FP32_BF16STORE) return fn(Engine<3, float, __hip_bfloat16, float>{});
+  return LBM_E_UNSUPPORTED;
+}
+
+void reset_nci_state(lbm_ctx* c) {
+  const Layout& L = c->L;
+  (void)hipMemsetAsync(c->ws + L.off_flags, 0, 2 * (size_t)L.ntiles * 4, c->stream);
+  (void)hipMemsetAsync(c->ws + L.off_cnt, 0, 64, c->stream);
+  (void)hipMemsetAsync(c->J(), 0, (size_t)c->p.dim * L.S * real_size(c->p.precision), c->stream);
+}
+
+// Mixture and forcing constants of the current parameters (Sec. 2.1).
+void set_phys(lbm_ctx* c, double mean_phi) {
+  const lbm_params& p = c->p;
+  const double cs2 = 1.0 / 3.0;
+  const double rho_l = 1.0, rho_g = 1.0 / p.density_ratio;
+  const double nu_l = cs2 * (p.tau - 0.5), nu_g = p.visc_ratio * nu_l;
+  Phys& P = c->phys;
+  P.rho_g = rho_g;
+  P.drho = rho_l - rho_g;
+  P.mu_a = rho_g * nu_g;
+  P.mu_b = rho_l * nu_l - rho_g * nu_g;
+  P.beta4 = 4.0 * 12.0 * p.sigma / p.width;
+  P.kappa = 1.5 * p.sigma * p.width;
+  P.rho_mean = rho_g + (rho_l - rho_g) * mean_phi;
+  for (int a = 0; a < 3; ++a) P.g[a] = a < p.dim ? p.body_force[a] : 0.0;
+  P.kc = p.cac_compress ? p.mobility * 4.0 / p.width : 0.0;
+  const double cs2_phi = p.dim == 2 ? 1.0 / 3.0 : 0.25;
+  P.inv_tau_phi = 1.0 / (0.5 + p.mobility / cs2_phi);
+  P.pstar_ref = p.pstar_ref;
+  P.eps_n = p.eps_n;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+
+extern "C" {
+
+void lbm_default_params(lbm_params* p) {
+  if (!p) return;
+  std::memset(p, 0, sizeof(*p));
+  p->dim = 2;
+  p->nx = 128;
+  p->ny = 128;
+  p->nz = 1;
+  p->precision = LBM_FP64;
+  p->tau = 1.0;
+  p->visc_ratio = 1.0;
+  p->mobility = 0.1;
+  p->width = 4.0;
+  p->sigma = 1e-3;
+  p->density_ratio = 1.0;
+  p->a_rep = 1e-3;
+  p->nci_window = 3;
+  p->q_th = 0.125;
+  p->eta = 0.1;
+  p->cos_opp = -0.8;
+  p->h0 = 1.0;
+  p->p_exp = 4.0;
+  p->eps_n = 1e-12;
+  p->eps_q = 1e-6;
+  p->tie_eps = 1e-6;
+  p->rep_orient = 0;
+  p->dispersed = -1;
+  p->cac_compress = 1;
+  p->diag_interval = 0;
+  p->pstar_ref = 0.0;
+}
+
+size_t lbm_workspace_bytes(const lbm_params* p) {
+  if (!valid_params(p, nullptr)) return 0;
+  return make_layout(p).total;
+}
+
+int lbm_create(const lbm_params* p, void* dev_workspace, size_t ws_bytes, void* hip_stream,
+               lbm_ctx** out) {
+  if (!out) return LBM_E_INVALID;
+  *out = nullptr;
+  std::string why;
+  if (!valid_params(p, &why)) {
+    g_create_error = why;
+    return LBM_E_INVALID;
+  }
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) {
+    g_create_error = "no HIP device";
+    return LBM_E_HIP;
+  }
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, dev) != hipSuccess) {
+    g_create_error = "hipGetDeviceProperties failed";
+    return LBM_E_HIP;
+  }
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) {
+    g_create_error = std::string("this library is built for gfx950, device is ") + prop.gcnArchName;
+    return LBM_E_UNSUPPORTED;
+  }
+  lbm_ctx* c = new lbm_ctx();
+  c->p = *p;
+  c->dev = dev;
+  c->L = make_layout(p);
+  if (dev_workspace) {
+    if (ws_bytes < c->L.total || ((uintptr_t)dev_workspace & 255)) {
+      g_create_error = "workspace too small or not 256-byte aligned";
+      delete c;
+      return LBM_E_OOM;
+    }
+    c->ws = (char*)dev_workspace;
+  } else {
+    if (hipMalloc((void**)&c->ws, c->L.total) != hipSuccess) {
+      g_create_error = "device allocation of the workspace failed";
+      delete c;
+      return LBM_E_OOM;
+    }
+    c->own_ws = true;
+  }
+  if (hip_stream) {
+    c->stream = (hipStream_t)hip_stream;
+  } else {
+    if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+      if (c->own_ws) (void)hipFree(c->ws);
+      delete c;
+      g_create_error = "stream creation failed";
+      return LBM_E_HIP;
+    }
+    c->own_stream = true;
+  }
+  Geo& G = c->geo;
+  G.nx = p->nx;
+  G.ny = p->ny;
+  G.nz = p->nz;
+  G.nbx = (p->nx + BX - 1) / BX;
+  G.nby = (p->ny + BY - 1) / BY;
+  G.S = c->L.S;
+  G.ntx = c->L.ntx;
+  G.nty = c->L.nty;
+  G.ntz = c->L.ntz;
+  NciP& A = c->nci;
+  A.a_rep = p->a_rep;
+  A.q_th = p->q_th;
+  A.eta = p->eta;
+  A.cos_opp = p->cos_opp;
+  A.h0 = p->h0;
+  A.p_exp = p->p_exp;
+  A.eps_n = p->eps_n;
+  A.eps_q = p->eps_q;
+  A.tie_eps = p->tie_eps;
+  A.width = p->width;
+  A.w = p->nci_window;
+  A.orient = p->rep_orient;
+  set_phys(c, 0.0);
+  (void)hipMemsetAsync(c->ws, 0, c->L.total, c->stream);
+  if (hipStreamSynchronize(c->stream) != hipSuccess) {
+    g_create_error = "workspace clear failed";
+    lbm_destroy(c);
+    return LBM_E_HIP;
+  }
+  *out = c;
+  return LBM_OK;
+}
+
+void lbm_destroy(lbm_ctx* c) {
+  if (!c) return;
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
+  if (c->own_ws && c->ws) (void)hipFree(c->ws);
+  if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+  delete c;
+}
+
+const char* lbm_last_error(const lbm_ctx* c) { return c ? c->err.c_str() : g_create_error.c_str(); }
+
+int lbm_init_fields(lbm_ctx* c, const double* phi, const double* u, const double* pstar) {
+  if (!c || !phi) return c ? c->fail(LBM_E_INVALID, "phi is required") : LBM_E_INVALID;
+  double acc = 0.0;
+  for (long long i = 0; i < c->L.N; ++i) acc += phi[i];
+  const double mean_phi = acc / (double)c->L.N;
+  set_phys(c, mean_phi);
+  c->dispersed = c->p.dispersed >= 0 ? c->p.dispersed : (mean_phi < 0.5 ? 1 : 0);
+  reset_nci_state(c);
+  const int rc = dispatch(c, [&](auto E) { return decltype(E)::init(c, phi, u, pstar); });
+  if (rc != LBM_OK) return rc;
+  c->step = 0;
+  c->hist_count = 0;
+  c->initialised = true;
+  return LBM_OK;
+}
+
+int lbm_step(lbm_ctx* c, int n) {
+  if (!c) return LBM_E_INVALID;
+  if (n < 0) return c->fail(LBM_E_INVALID, "negative step count");
+  if (!c->initialised) return c->fail(LBM_E_STATE, "lbm_step before lbm_init_fields");
+  return dispatch(c, [&](auto E) { return decltype(E)::step(c, n); });
+}
+
+long lbm_step_count(const lbm_ctx* c) { return c ? c->step : -1; }
+
+int lbm_diag_history(lbm_ctx* c, lbm_diag* out, int max) {
+  if (!c || (!out && max > 0)) return LBM_E_INVALID;
+  HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+  const int have = std::min(c->hist_count, HIST);
+  std::vector<double> buf((size_t)(HIST + 1) * 2 * NPART);
+  HIP_OR_FAIL(c, hipMemcpy(buf.data(), c->red(0), buf.size() * 8, hipMemcpyDeviceToHost));
+  int k = 0;
+  for (int j = std::max(0, c->hist_count - HIST); j < c->hist_count && k < max; ++j, ++k) {
+    fill_diag(&buf[(size_t)(1 + (j % HIST)) * 2 * NPART], c->hist_step[j % HIST], &out[k]);
+  }
+  (void)have;
+  return k;
+}
+
+int lbm_sync(lbm_ctx* c) {
+  if (!c) return LBM_E_INVALID;
+  HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+  if (c->p.diag_interval > 0 && c->hist_count > 0) {
+    std::vector<lbm_diag> h(HIST);
+    const int n = lbm_diag_history(c, h.data(), HIST);
+    for (int i = 0; i < n; ++i)
+      if (!h[i].finite) return c->fail(LBM_E_DIVERGED, "non-finite value at step " + std::to_string(h[i].step));
+  }
+  return LBM_OK;
+}
+
+#define NEED_INIT(c)                                                              \
+  do {                                                                            \
+    if (!(c)) return LBM_E_INVALID;                                               \
+    if (!(c)->initialised) return (c)->fail(LBM_E_STATE, "context not initialised"); \
+  } while (0)
+
+int lbm_get_phi(lbm_ctx* c, double* out) {
+  NEED_INIT(c);
+  if (!out) return c->fail(LBM_E_INVALID, "null output");
+  return dispatch(c, [&](auto E) { return decltype(E)::get_phi(c, out); });
+}
+
+int lbm_get_pstar(lbm_ctx* c, double* out) {
+  NEED_INIT(c);
+  if (!out) return c->fail(LBM_E_INVALID, "null output");
+  return dispatch(c, [&](auto E) { return decltype(E)::get_macro(c, 0, out); });
+}
+
+int lbm_get_rho(lbm_ctx* c, double* out) {
+  NEED_INIT(c);
+  if (!out) return c->fail(LBM_E_INVALID, "null output");
+  return dispatch(c, [&](auto E) { return decltype(E)::get_macro(c, 1, out); });
+}
+
+int lbm_get_u(lbm_ctx* c, double* out) {
+  NEED_INIT(c);
+  if (!out) return c->fail(LBM_E_INVALID, "null output");
+  return dispatch(c, [&](auto E) { return decltype(E)::get_macro(c, 2, out); });
+}
+
+int lbm_get_force(lbm_ctx* c, double* out) {
+  NEED_INIT(c);
+  if (!out) return c->fail(LBM_E_INVALID, "null output");
+  return dispatch(c, [&](auto E) { return decltype(E)::get_macro(c, 3, out); });
+}
+
+int lbm_get_nci(lbm_ctx* c, int* chi, int* partner, double* J) {
+  NEED_INIT(c);
+  return dispatch(c, [&](auto E) { return decltype(E)::get_nci(c, chi, partner, J); });
+}
+
+int lbm_diagnostics(lbm_ctx* c, lbm_diag* out) {
+  NEED_INIT(c);
+  if (!out) return c->fail(LBM_E_INVALID, "null output");
+  return dispatch(c, [&](auto E) { return decltype(E)::diagnostics(c, out); });
+}
+
+int lbm_lattice(int dim, int which, int* c) {
+  if (dim != 2 && dim != 3) return LBM_E_INVALID;
+  const int q = which == 0 ? q_hydro(dim) : q_phase(dim);
+  if (c) {
+    for (int i = 0; i < q; ++i) {
+      if (dim == 2) {
+        c[3 * i] = Hydro<2>::cx[i];
+        c[3 * i + 1] = Hydro<2>::cy[i];
+        c[3 * i + 2] = 0;
+      } else if (which == 0) {
+        c[3 * i] = Hydro<3>::cx[i];
+        c[3 * i + 1] = Hydro<3>::cy[i];
+        c[3 * i + 2] = Hydro<3>::cz[i];
+      } else {
+        c[3 * i] = Phase<3>::cx[i];
+        c[3 * i + 1] = Phase<3>::cy[i];
+        c[3 * i + 2] = Phase<3>::cz[i];
+      }
+    }
+  }
+  return q;
+}
+
+int lbm_get_populations(lbm_ctx* c, int x0, int y0, int z0, int bx, int by, int bz, double* f,
+                        double* g) {
+  NEED_INIT(c);
+  if (bx < 1 || by < 1 || bz < 1 || (c->p.dim == 2 && bz != 1))
+    return c->fail(LBM_E_INVALID, "bad box");
+  return dispatch(c, [&](auto E) { return decltype(E)::get_pop(c, x0, y0, z0, bx, by, bz, f, g); });
+}
+
+int lbm_set_populations(lbm_ctx* c, const double* f, const double* g) {
+  if (!c) return LBM_E_INVALID;
+  if (!f || !g) return c->fail(LBM_E_INVALID, "null populations");
+  // mean phi (for the buoyancy reference) from the phase-field populations
+  const long long N = c->L.N;
+  const int qg = q_phase(c->p.dim);
+  double acc = 0.0;
+  for (long long i = 0; i < N; ++i) {
+    double s = 0.0;
+    for (int k = 0; k < qg; ++k) s += g[(size_t)k * N + i];
+    acc += s;
+  }
+  const double mean_phi = acc / (double)N;
+  set_phys(c, mean_phi);
+  c->dispersed = c->p.dispersed >= 0 ? c->p.dispersed : (mean_phi < 0.5 ? 1 : 0);
+  reset_nci_state(c);
+  const int rc = dispatch(c, [&](auto E) { return decltype(E)::set_pop(c, f, g); });
+  if (rc != LBM_OK) return rc;
+  c->step = 0;
+  c->hist_count = 0;
+  c->initialised = true;
+  return LBM_OK;
+}
+
+// Raw state: header {magic, step, rho_mean, dispersed} + f + g as stored.
+namespace {
+struct StateHeader {
+  unsigned long long magic;
+  long long step;
+  double rho_mean;
+  long long dispersed;
+  long long nx, ny, nz, precision;
+};
+constexpr unsigned long long STATE_MAGIC = 0x4c424d5354415445ULL;  // "LBMSTATE"
+size_t pop_bytes(const lbm_ctx* c) {
+  return c->L.off_phi;  // f and g are the first two regions of the workspace
+}
+}  // namespace
+
+size_t lbm_state_bytes(const lbm_ctx* c) { return c ? sizeof(StateHeader) + pop_bytes(c) : 0; }
+
+int lbm_save_state(lbm_ctx* c, void* buf, size_t bytes) {
+  NEED_INIT(c);
+  if (!buf || bytes < lbm_state_bytes(c)) return c->fail(LBM_E_INVALID, "state buffer too small");
+  StateHeader h{STATE_MAGIC, c->step, c->phys.rho_mean, c->dispersed, c->p.nx, c->p.ny, c->p.nz,
+                c->p.precision};
+  std::memcpy(buf, &h, sizeof(h));
+  HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+  HIP_OR_FAIL(c, hipMemcpy((char*)buf + sizeof(h), c->ws, pop_bytes(c), hipMemcpyDeviceToHost));
+  return LBM_OK;
+}
+
+int lbm_load_state(lbm_ctx* c, const void* buf, size_t bytes) {
+  if (!c) return LBM_E_INVALID;
+  if (!buf || bytes < lbm_state_bytes(c)) return c->fail(LBM_E_INVALID, "state buffer too small");
+  StateHeader h;
+  std::memcpy(&h, buf, sizeof(h));
+  if (h.magic != STATE_MAGIC || h.nx != c->p.nx || h.ny != c->p.ny || h.nz != c->p.nz ||
+      h.precision != c->p.precision)
+    return c->fail(LBM_E_INVALID, "state does not match this context");
+  HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+  HIP_OR_FAIL(c, hipMemcpy(c->ws, (const char*)buf + sizeof(h), pop_bytes(c), hipMemcpyHostToDevice));
+  c->step = h.step;
+  c->dispersed = (int)h.dispersed;
+  c->phys.rho_mean = h.rho_mean;
+  reset_nci_state(c);
+  HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+  c->hist_count = 0;
+  c->initialised = true;
+  return LBM_OK;
+}
+
+int lbm_timing(lbm_ctx* c, int enable) {
+  if (!c) return LBM_E_INVALID;
+  if (enable && c->ev.empty()) {
+    c->ev.resize(2 * EV_PAIRS);
+    c->ev_kind.resize(EV_PAIRS);
+    for (auto& e : c->ev) HIP_OR_FAIL(c, hipEventCreate(&e));
+  }
+  if (!enable) {
+    const int rc = flush_timing(c);
+    if (rc != LBM_OK) return rc;
+  }
+  c->timing = enable != 0;
+  return LBM_OK;
+}
+
+int lbm_kernel_times(lbm_ctx* c, double* ms, long* counts) {
+  if (!c || !ms || !counts) return LBM_E_INVALID;
+  const int rc = flush_timing(c);
+  if (rc != LBM_OK) return rc;
+  for (int k = 0; k < 4; ++k) {
+    ms[k] = c->k_ms[k];
+    counts[k] = c->k_cnt[k];
+    c->k_ms[k] = 0.0;
+    c->k_cnt[k] = 0;
+  }
+  return LBM_OK;
+}
+
+int lbm_batch_step(lbm_ctx* const* ctxs, int count, int n) {
+  if (!ctxs || count < 0 || n < 0) return LBM_E_INVALID;
+  for (int i = 0; i < count; ++i) {
+    const int rc = lbm_step(ctxs[i], n);
+    if (rc != LBM_OK) return rc;
+  }
+  return LBM_OK;
+}
+
+}  // extern "C"

@@ -53,10 +53,12 @@ class Params:
     p_exp: float = 4.0
     eps_n: float = 1e-12
     eps_q: float = 1e-6
+    tie_eps: float = 1e-6        # facing scores within tie_eps of the best count as tied
     rep_orient: int = 0          # 0: along n(x); +1: toward partner; -1: away from partner
     dispersed: int = -1          # 1: droplets {phi>1/2}; 0: bubbles {phi<1/2}; -1: minority phase
     cac_compress: int = 1        # 0 switches the counter-gradient flux off (diffusion test)
     diag_interval: int = 0       # periodic on-device diagnostics every K steps (0: never)
+    pstar_ref: float = 0.0       # reference p* of the 16-bit population encoding
 
     @property
     def n_cells(self) -> int:

@@ -578,3 +578,21 @@ def test_paper_parameter_values():
         assert getattr(p, k) == v, k
     w = p.nci_window
     assert (2 * w + 1) ** 3 - 1 == g["probes_per_gated_cell_3d"]
+
+
+def test_storage_rounding_knob():
+    """The oracle's test knob rounds stored populations to the named format."""
+    st = W.config_collision_2d()
+    for mode, dtype in ((1, np.float32), (2, np.float16)):
+        o = O.Oracle(st.params, store_round=mode)
+        o.init_fields(st.phi, st.u)
+        o.step(3)
+        f, g = o.get_populations()
+        assert np.array_equal(f, f.astype(dtype).astype(np.float64))
+        assert np.array_equal(g, g.astype(np.float32).astype(np.float64))
+    o = O.Oracle(st.params, store_round=3)
+    o.init_fields(st.phi, st.u)
+    o.step(3)
+    f, _ = o.get_populations()
+    bits = f.astype(np.float32).view(np.uint32)
+    assert np.all((bits & 0xFFFF) == 0)
