@@ -24,6 +24,7 @@ namespace lbm {
 constexpr int BX = 64;   // cells along x per block (one wave)
 constexpr int BY = 4;    // rows per block
 constexpr int NT = BX * BY;
+constexpr int NT_NCI = 512;   // near-contact kernel: two blocks of 512 per CU fit its LDS
 constexpr int PHI_HALO = 4;   // window radius 3 + 1 for the normals
 constexpr int NQ_HALO = 3;    // window radius
 constexpr int NPART = 8;      // doubles per block in the reduction scratch
@@ -107,6 +108,17 @@ struct Store<__hip_bfloat16> {
   __device__ static void st(__hip_bfloat16* p, float v, float off) { *p = __float2bfloat16(v - off); }
 };
 
+// Element e of a population plane.  With OFF32 the byte offset is formed in 32
+// bits (valid while every plane is below 4 GiB), so the access can use the
+// uniform plane base in scalar registers plus a 32-bit per-lane offset.
+template <bool OFF32, typename E>
+__device__ __forceinline__ E* plane_at(E* base, unsigned e) {
+  if constexpr (OFF32)
+    return (E*)((char*)base + (unsigned)(e * (unsigned)sizeof(E)));
+  else
+    return base + e;
+}
+
 __device__ __forceinline__ float m_sqrt(float a) { return sqrtf(a); }
 __device__ __forceinline__ double m_sqrt(double a) { return sqrt(a); }
 __device__ __forceinline__ float m_acosh(float a) { return acoshf(a); }
@@ -185,9 +197,9 @@ __global__ __launch_bounds__(NT) void k_phi(const GS* __restrict__ g, T* __restr
                                             unsigned* __restrict__ flags,
                                             unsigned* __restrict__ list,
                                             unsigned* __restrict__ cnt,
-                                            unsigned* __restrict__ nci_count, int nci_on, T q_th,
-                                            int ttx, int tty, int ttz) {
+                                            unsigned* __restrict__ nci_count, int nci_on, T q_th) {
   using P = Phase<DIM>;
+  using TL = NciTile<DIM, T>;
   if (nci_on && blockIdx.x == 0 && threadIdx.x == 0) *nci_count = 0u;
   const int t = swizzled_block();
   const int bx = t % geo.nbx, r = t / geo.nbx, by = r % geo.nby, z = r / geo.nby;
@@ -210,7 +222,7 @@ __global__ __launch_bounds__(NT) void k_phi(const GS* __restrict__ g, T* __restr
     const T pc = s < (T)0 ? (T)0 : (s > (T)1 ? (T)1 : s);
     const T q = pc * ((T)1 - pc);
     if (q >= q_th) {
-      const unsigned tile = (unsigned)(x / ttx + geo.ntx * (y / tty + geo.nty * (z / ttz)));
+      const unsigned tile = (unsigned)(x / TL::TX + geo.ntx * (y / TL::TY + geo.nty * (z / TL::TZ)));
       if (flags[tile] == 0u && atomicExch(&flags[tile], 1u) == 0u) list[atomicAdd(cnt, 1u)] = tile;
     }
   }
@@ -220,8 +232,36 @@ __global__ __launch_bounds__(NT) void k_phi(const GS* __restrict__ g, T* __restr
 // (a2) near-contact detection, pairing and repulsive flux (Sec. 2.3)
 // ---------------------------------------------------------------------------
 
+// Wrapped coordinate for offsets within one tile + halo of the box.
+__device__ __forceinline__ int wrap_near(int v, int n) {
+  if (n >= 32) return v < 0 ? v + n : (v >= n ? v - n : v);
+  return wrapi(v, n);
+}
+
+// Lexicographic minimum of (d2, dot) over the lanes of an 8-lane group.
+template <typename T>
+__device__ __forceinline__ void group_min(int& d2, T& dot) {
+#pragma unroll
+  for (int o = 1; o < 8; o <<= 1) {
+    const int d2o = __shfl_xor(d2, o, 64);
+    const T doto = __shfl_xor(dot, o, 64);
+    if (d2o < d2 || (d2o == d2 && doto < dot)) {
+      d2 = d2o;
+      dot = doto;
+    }
+  }
+}
+
+// Per listed tile: (1) phi with a halo of 4 into LDS; (2) q on tile + 3 and
+// n only where q >= q_th (n is read only after a candidate passes the gate);
+// (3) the gated cells of the tile are listed; (4) each gated cell gets an
+// 8-lane group whose lanes scan one window plane each (dz in 3D, dy in 2D):
+// pass 0 finds the smallest |r|^2 and the smallest n(x).n(y) at it, pass 1 the
+// first candidate in scan order within tie_eps of that dot; the planes are
+// combined with wave shuffles; (5) the group leader builds J (Sec. 2.3.3) and
+// the tile's J is written from LDS, zero for cells without a partner.
 template <int DIM, typename T, bool DEBUG>
-__global__ __launch_bounds__(NT) void k_nci(const T* __restrict__ phi, T* __restrict__ J,
+__global__ __launch_bounds__(NT_NCI) void k_nci(const T* __restrict__ phi, T* __restrict__ J,
                                             int* __restrict__ chi_out, int* __restrict__ part_out,
                                             const unsigned* __restrict__ list,
                                             const unsigned* __restrict__ cnt,
@@ -232,24 +272,31 @@ __global__ __launch_bounds__(NT) void k_nci(const T* __restrict__ phi, T* __rest
   using TL = NciTile<DIM, T>;
   using L = Hydro<DIM>;
   constexpr int TX = TL::TX, TY = TL::TY, TZ = TL::TZ;
+  constexpr int TC = TX * TY * TZ;
   constexpr int PX = TX + 2 * PHI_HALO, PY = TY + 2 * PHI_HALO, PZ = DIM == 3 ? TZ + 2 * PHI_HALO : 1;
   constexpr int NX = TX + 2 * NQ_HALO, NY = TY + 2 * NQ_HALO, NZ = DIM == 3 ? TZ + 2 * NQ_HALO : 1;
   constexpr int NPH = PX * PY * PZ, NNQ = NX * NY * NZ;
   __shared__ T phs[NPH];
   __shared__ T nqs[DIM + 1][NNQ];
+  __shared__ short glist[TC];          // gated tile cells
+  __shared__ short gslot[TC];          // tile cell -> index in glist, or -1
+  __shared__ T gJ[TC][DIM];            // result per gated cell
+  __shared__ int gpart[TC];            // packed partner offset + 1 (0: no partner)
+  __shared__ int s_ng;
 
   // Flags of the previous step's parity are cleared here, before the next
   // step's phi kernel sets them again.
   {
     const unsigned nother = *cnt_other;
-    for (unsigned k = blockIdx.x * NT + threadIdx.x; k < nother; k += gridDim.x * NT)
+    for (unsigned k = blockIdx.x * NT_NCI + threadIdx.x; k < nother; k += gridDim.x * NT_NCI)
       flags_other[list_other[k]] = 0u;
   }
   const unsigned ntiles = *cnt;
   const T q_th = (T)np.q_th, eta = (T)np.eta, cos_opp = (T)np.cos_opp, eps_n = (T)np.eps_n,
-          eps_q = (T)np.eps_q;
+          eps_q = (T)np.eps_q, tie = (T)np.tie_eps;
   const int w = np.w;
-  const int wz = DIM == 3 ? w : 0;
+  const int lane8 = threadIdx.x & 7, grp = threadIdx.x >> 3;
+  constexpr int NGRP = NT_NCI / 8;
   unsigned my_active = 0;
   for (unsigned k = blockIdx.x; k < ntiles; k += gridDim.x) {
     const unsigned t = list[k];
@@ -257,91 +304,136 @@ __global__ __launch_bounds__(NT) void k_nci(const T* __restrict__ phi, T* __rest
     const int ty = (int)((t / (unsigned)geo.ntx) % (unsigned)geo.nty);
     const int tz = (int)(t / ((unsigned)geo.ntx * (unsigned)geo.nty));
     const int ox = tx * TX, oy = ty * TY, oz = tz * TZ;
-    for (int e = threadIdx.x; e < NPH; e += NT) {
+    if (threadIdx.x == 0) s_ng = 0;
+    // (1) phi tile with halo
+    for (int e = threadIdx.x; e < NPH; e += NT_NCI) {
       const int ex = e % PX, ey = (e / PX) % PY, ez = e / (PX * PY);
-      const int gx = wrapi(ox + ex - PHI_HALO, geo.nx), gy = wrapi(oy + ey - PHI_HALO, geo.ny);
-      const int gz = DIM == 3 ? wrapi(oz + ez - PHI_HALO, geo.nz) : 0;
+      const int gx = wrap_near(ox + ex - PHI_HALO, geo.nx), gy = wrap_near(oy + ey - PHI_HALO, geo.ny);
+      const int gz = DIM == 3 ? wrap_near(oz + ez - PHI_HALO, geo.nz) : 0;
       phs[e] = phi[gx + geo.nx * (gy + geo.ny * gz)];
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < NNQ; e += NT) {
+    // (2) indicator everywhere on tile + 3, normal where the indicator passes the gate
+    for (int e = threadIdx.x; e < NNQ; e += NT_NCI) {
       const int ex = e % NX, ey = (e / NX) % NY, ez = e / (NX * NY);
       const int c = (ex + 1) + PX * ((ey + 1) + PY * (DIM == 3 ? ez + 1 : 0));
-      T gr[3], lap;
-      grad_lap<DIM, T>([&](int i) { return phs[c + L::cx[i] + PX * (L::cy[i] + PY * L::cz[i])]; }, gr,
-                       lap);
-      T mag = gr[0] * gr[0] + gr[1] * gr[1];
-      if (DIM == 3) mag += gr[2] * gr[2];
-      mag = m_sqrt(mag);
-      const T den = mag + eps_n;
-#pragma unroll
-      for (int a = 0; a < DIM; ++a) nqs[a][e] = gr[a] / den;
       const T ph = phs[c];
       const T pc = ph < (T)0 ? (T)0 : (ph > (T)1 ? (T)1 : ph);
-      nqs[DIM][e] = pc * ((T)1 - pc);
+      const T q = pc * ((T)1 - pc);
+      nqs[DIM][e] = q;
+      if (q >= q_th) {
+        T gr[3], lap;
+        grad_lap<DIM, T>([&](int i) { return phs[c + L::cx[i] + PX * (L::cy[i] + PY * L::cz[i])]; },
+                         gr, lap);
+        T mag = gr[0] * gr[0] + gr[1] * gr[1];
+        if (DIM == 3) mag += gr[2] * gr[2];
+        mag = m_sqrt(mag);
+        const T den = mag + eps_n;
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) nqs[a][e] = gr[a] / den;
+      }
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < TX * TY * TZ; e += NT) {
+    // (3) list the gated cells of the tile
+    for (int e = threadIdx.x; e < TC; e += NT_NCI) {
       const int lx = e % TX, ly = (e / TX) % TY, lz = e / (TX * TY);
-      const int gx = ox + lx, gy = oy + ly, gz = oz + lz;
-      if (gx >= geo.nx || gy >= geo.ny || gz >= geo.nz) continue;
-      const int idx = gx + geo.nx * (gy + geo.ny * gz);
+      const bool inside = ox + lx < geo.nx && oy + ly < geo.ny && oz + lz < geo.nz;
+      const int cc = (lx + NQ_HALO) + NX * ((ly + NQ_HALO) + NY * (DIM == 3 ? lz + NQ_HALO : 0));
+      short slot = -1;
+      if (inside && nqs[DIM][cc] >= q_th) {
+        slot = (short)atomicAdd(&s_ng, 1);
+        glist[slot] = (short)e;
+      }
+      gslot[e] = slot;
+    }
+    __syncthreads();
+    const int ng = s_ng;
+    // (4) partner search, one 8-lane group per gated cell, one plane per lane
+    for (int base = 0; base < ng; base += NGRP) {
+      const int gi = base + grp;
+      const bool cell_ok = gi < ng;
+      const int e = cell_ok ? glist[gi] : 0;
+      const int lx = e % TX, ly = (e / TX) % TY, lz = e / (TX * TY);
       const int cc = (lx + NQ_HALO) + NX * ((ly + NQ_HALO) + NY * (DIM == 3 ? lz + NQ_HALO : 0));
       const T qx = nqs[DIM][cc];
-      T Jv[3] = {0, 0, 0};
-      int found = 0, bdx = 0, bdy = 0, bdz = 0;
-      if (qx >= q_th) {
-        T nxv[3];
+      T nxv[3] = {0, 0, 0};
 #pragma unroll
-        for (int a = 0; a < DIM; ++a) nxv[a] = nqs[a][cc];
-        const T qm = qx > eps_q ? qx : eps_q;
-        const T tol = eta * qm;
-        const T tie = (T)np.tie_eps;
-        int bd2 = 0;
-        T bdot = 0;
-        // pass 0: smallest |r|^2 among accepted candidates, and the smallest
-        // n(x).n(y) at that distance; pass 1: the first candidate in scan order
-        // at that distance whose dot lies within tie_eps of the smallest.
-        for (int pass = 0; pass < 2; ++pass) {
-          bool done = false;
-          for (int dz = -wz; dz <= wz && !done; ++dz)
-            for (int dy = -w; dy <= w && !done; ++dy)
-              for (int dx = -w; dx <= w; ++dx) {
-                if ((dx | dy | dz) == 0) continue;
-                const int d2 = dx * dx + dy * dy + dz * dz;
-                if (pass == 1 && d2 != bd2) continue;
-                const int cy_ = cc + dx + NX * (dy + NY * dz);
-                const T qy = nqs[DIM][cy_];
-                if (!(qy >= q_th)) continue;
-                if (!(m_abs(qy - qx) <= tol)) continue;
-                T dot = nxv[0] * nqs[0][cy_];
-                dot += nxv[1] * nqs[1][cy_];
-                if (DIM == 3) dot += nxv[2] * nqs[2][cy_];
-                if (!(dot <= cos_opp)) continue;
-                if (pass == 0) {
-                  if (!found || d2 < bd2 || (d2 == bd2 && dot < bdot)) {
-                    found = 1;
-                    bd2 = d2;
-                    bdot = dot;
-                  }
-                } else if (dot <= bdot + tie) {
-                  bdx = dx;
-                  bdy = dy;
-                  bdz = dz;
-                  bdot = dot;
-                  done = true;
-                  break;
-                }
-              }
-          if (!found) break;
-        }
-        if (found) {
+      for (int a = 0; a < DIM; ++a) nxv[a] = nqs[a][cc];
+      const T tol = eta * (qx > eps_q ? qx : eps_q);
+      const int plane = lane8 - w;                  // dz (3D) or dy (2D)
+      const bool lane_ok = cell_ok && lane8 <= 2 * w;
+      // pass 0
+      int bd2 = 1 << 30;
+      T bdot = (T)0;
+      if (lane_ok) {
+        const int dz0 = DIM == 3 ? plane : 0, ylo = DIM == 3 ? -w : plane, yhi = DIM == 3 ? w : plane;
+        for (int dy = ylo; dy <= yhi; ++dy)
+          for (int dx = -w; dx <= w; ++dx) {
+            if ((dx | dy | dz0) == 0) continue;
+            const int cy_ = cc + dx + NX * (dy + NY * dz0);
+            const T qy = nqs[DIM][cy_];
+            if (!(qy >= q_th)) continue;
+            if (!(m_abs(qy - qx) <= tol)) continue;
+            T dot = nxv[0] * nqs[0][cy_];
+            dot += nxv[1] * nqs[1][cy_];
+            if (DIM == 3) dot += nxv[2] * nqs[2][cy_];
+            if (!(dot <= cos_opp)) continue;
+            const int d2 = dx * dx + dy * dy + dz0 * dz0;
+            if (d2 < bd2 || (d2 == bd2 && dot < bdot)) {
+              bd2 = d2;
+              bdot = dot;
+            }
+          }
+      }
+      group_min(bd2, bdot);
+      const bool found = bd2 < (1 << 30);
+      // pass 1: first candidate in scan order at distance bd2 within tie_eps of bdot
+      int key = 1 << 30;
+      if (lane_ok && found) {
+        const int dz0 = DIM == 3 ? plane : 0, ylo = DIM == 3 ? -w : plane, yhi = DIM == 3 ? w : plane;
+        bool done = false;
+        for (int dy = ylo; dy <= yhi && !done; ++dy)
+          for (int dx = -w; dx <= w; ++dx) {
+            const int d2 = dx * dx + dy * dy + dz0 * dz0;
+            if (d2 != bd2) continue;
+            const int cy_ = cc + dx + NX * (dy + NY * dz0);
+            const T qy = nqs[DIM][cy_];
+            if (!(qy >= q_th)) continue;
+            if (!(m_abs(qy - qx) <= tol)) continue;
+            T dot = nxv[0] * nqs[0][cy_];
+            dot += nxv[1] * nqs[1][cy_];
+            if (DIM == 3) dot += nxv[2] * nqs[2][cy_];
+            if (!(dot <= cos_opp)) continue;
+            if (dot <= bdot + tie) {
+              // scan-order key: plane index, then row, then column
+              key = ((lane8 * 16) + (dy + 8)) * 16 + (dx + 8);
+              done = true;
+              break;
+            }
+          }
+      }
+#pragma unroll
+      for (int o = 1; o < 8; o <<= 1) {
+        const int ko = __shfl_xor(key, o, 64);
+        key = ko < key ? ko : key;
+      }
+      // (5) the group leader builds the repulsive flux of its cell
+      if (cell_ok && lane8 == 0) {
+        T Jv[3] = {0, 0, 0};
+        int packed = 0;
+        if (found && key < (1 << 30)) {
+          const int kdx = (key & 15) - 8, kdy = ((key >> 4) & 15) - 8, kpl = (key >> 8) - w;
+          const int bdx = kdx, bdy = DIM == 3 ? kdy : kpl, bdz = DIM == 3 ? kpl : 0;
           const int cy_ = cc + bdx + NX * (bdy + NY * bdz);
           const T qy = nqs[DIM][cy_];
+          T dot = nxv[0] * nqs[0][cy_];
+          dot += nxv[1] * nqs[1][cy_];
+          if (DIM == 3) dot += nxv[2] * nqs[2][cy_];
           T qcl = (T)0.5 * (qx + qy);
           if (qcl < eps_q) qcl = eps_q;
           if (qcl > (T)0.25 - eps_q) qcl = (T)0.25 - eps_q;
-          const T ff = -bdot > (T)0 ? -bdot : (T)0;
+          const T ff = -dot > (T)0 ? -dot : (T)0;
+          packed = 1 + ((bdx + 8) | ((bdy + 8) << 5) | ((bdz + 8) << 10));
           if (ff != (T)0) {
             const T rn = m_sqrt((T)(bdx * bdx + bdy * bdy + bdz * bdz));
             const T rh[3] = {(T)bdx / rn, (T)bdy / rn, (T)bdz / rn};
@@ -379,17 +471,30 @@ __global__ __launch_bounds__(NT) void k_nci(const T* __restrict__ phi, T* __rest
 #pragma unroll
             for (int a = 0; a < DIM; ++a) Jv[a] = amp * ns[a];
           }
+          my_active += 1u;
         }
-      }
-      my_active += (unsigned)found;
 #pragma unroll
-      for (int a = 0; a < DIM; ++a) J[a * geo.S + idx] = Jv[a];
+        for (int a = 0; a < DIM; ++a) gJ[gi][a] = Jv[a];
+        gpart[gi] = packed;
+      }
+    }
+    __syncthreads();
+    // (6) the tile's flux (zero where there is no partner)
+    for (int e = threadIdx.x; e < TC; e += NT_NCI) {
+      const int lx = e % TX, ly = (e / TX) % TY, lz = e / (TX * TY);
+      const int gx = ox + lx, gy = oy + ly, gz = oz + lz;
+      if (gx >= geo.nx || gy >= geo.ny || gz >= geo.nz) continue;
+      const int idx = gx + geo.nx * (gy + geo.ny * gz);
+      const int sl = gslot[e];
+#pragma unroll
+      for (int a = 0; a < DIM; ++a) J[a * geo.S + idx] = sl >= 0 ? gJ[sl][a] : (T)0;
       if constexpr (DEBUG) {
         const long long N = (long long)geo.nx * geo.ny * geo.nz;
-        chi_out[idx] = found;
-        part_out[idx] = bdx;
-        part_out[N + idx] = bdy;
-        part_out[2 * N + idx] = bdz;
+        const int pk = sl >= 0 ? gpart[sl] : 0;
+        chi_out[idx] = pk != 0;
+        part_out[idx] = pk ? ((pk - 1) & 31) - 8 : 0;
+        part_out[N + idx] = pk ? (((pk - 1) >> 5) & 31) - 8 : 0;
+        part_out[2 * N + idx] = pk ? (((pk - 1) >> 10) & 31) - 8 : 0;
       }
     }
     __syncthreads();
@@ -422,17 +527,45 @@ __device__ __forceinline__ void block_partials(double v[NPART], double* __restri
   }
 }
 
-template <int DIM, int PAR, int MODE, typename T, typename FS, typename GS>
-__global__ __launch_bounds__(NT) void k_collide(FS* __restrict__ f, GS* __restrict__ g,
+// Base pointer of every population plane (kernel arguments, so they live in
+// scalar registers and each access is base + 32-bit lane offset).
+template <typename FS, typename GS>
+struct Planes {
+  FS* f[19];
+  GS* g[9];
+};
+
+// Mixture and forcing constants in the arithmetic type of the kernel.
+template <typename T>
+struct PhysT {
+  T rho_g, drho, mu_a, mu_b, beta4, kappa, rho_mean, g[3], kc, inv_tau_phi, eps_n;
+  T fref[19];   // w_i pstar_ref: offset of the 16-bit population encoding
+};
+
+__device__ __forceinline__ float m_rcp(float a) { return __builtin_amdgcn_rcpf(a); }
+__device__ __forceinline__ double m_rcp(double a) { return 1.0 / a; }
+
+// Post-collision populations, written as Hermite coefficients.  f^eq, the
+// regularised non-equilibrium part and S/2 all lie in the span of the Hermite
+// polynomials up to third order (the Guo term has no third-order part), so
+//   f*_i = w_i [ p* + c_i.A1/cs^2 + H2_i:B2/(2cs^4) + H3_i...B3/(6cs^6) ]
+// with A1 = u + F/(2 rho), B2 = uu + (1-omega) A2 + (uF + Fu)/(2 rho) and
+// B3 = uuu + (1-omega) S(u (x) A2); on these lattices the contractions reduce to
+//   H2:B2/(2cs^4) = 4.5 c.B2.c - 1.5 tr B2,
+//   H3...B3/(6cs^6) = 4.5 cu (cu^2 - u^2) + (1-omega)(13.5 cu c.A2.c - 4.5 cu trA2 - 9 c.A2.u).
+// Each opposite pair (c, -c) shares the even part and flips the odd part.
+template <int DIM, int PAR, int MODE, typename T, typename FS, typename GS, bool OFF32>
+__global__ __launch_bounds__(NT) void k_collide(Planes<FS, GS> pl,
                                                 const T* __restrict__ phi,
                                                 const T* __restrict__ J,
                                                 const unsigned* __restrict__ flags,
-                                                unsigned* __restrict__ cnt_other, Geo geo, Phys pp,
-                                                int nci_on, int ttx, int tty, int ttz,
+                                                unsigned* __restrict__ cnt_other, Geo geo,
+                                                PhysT<T> pp, int nci_on,
                                                 T* __restrict__ macro,
                                                 double* __restrict__ partials) {
   using H = Hydro<DIM>;
   using P = Phase<DIM>;
+  using TL = NciTile<DIM, T>;
   constexpr int Q = H::Q, QG = P::Q;
   if (nci_on && blockIdx.x == 0 && threadIdx.x == 0) *cnt_other = 0u;
   const int t = swizzled_block();
@@ -443,29 +576,30 @@ __global__ __launch_bounds__(NT) void k_collide(FS* __restrict__ f, GS* __restri
   if (MODE == MODE_STEP && !valid) return;
   if (valid) {
     const Nbr nb(x, y, z, geo);
-    const int idx = nb(0, 0, 0);
+    const unsigned idx = (unsigned)nb(0, 0, 0);
     const long long S = geo.S;
-    // ---- phase field around the cell: grad, lap, n, mu_phi
+    // ---- phase field around the cell: grad, lap, mu_phi
     T gr[3], lap;
-    grad_lap<DIM, T>([&](int i) { return phi[nb(H::cx[i], H::cy[i], H::cz[i])]; }, gr, lap);
-    const T ph = phi[idx];
+    grad_lap<DIM, T>([&](int i) { return *plane_at<OFF32>(phi, (unsigned)nb(H::cx[i], H::cy[i], H::cz[i])); },
+                     gr, lap);
+    const T ph = *plane_at<OFF32>(phi, idx);
     T gmag = gr[0] * gr[0] + gr[1] * gr[1];
     if (DIM == 3) gmag += gr[2] * gr[2];
     gmag = m_sqrt(gmag);
-    const T inv_g = (T)1 / (gmag + (T)pp.eps_n);
-    const T mu = (T)pp.beta4 * ph * (ph - (T)1) * (ph - (T)0.5) - (T)pp.kappa * lap;
+    const T inv_g = m_rcp(gmag + pp.eps_n);
+    const T mu = pp.beta4 * ph * (ph - (T)1) * (ph - (T)0.5) - pp.kappa * lap;
     // ---- mixture (linear rho, linear dynamic viscosity)
-    const T rho = (T)pp.rho_g + (T)pp.drho * ph;
-    const T inv_rho = (T)1 / rho;
-    const T nu = ((T)pp.mu_a + (T)pp.mu_b * ph) * inv_rho;
-    const T omega = (T)1 / ((T)0.5 + (T)3 * nu);
+    const T rho = pp.rho_g + pp.drho * ph;
+    const T inv_rho = m_rcp(rho);
+    const T nu = (pp.mu_a + pp.mu_b * ph) * inv_rho;
+    const T omega = m_rcp((T)0.5 + (T)3 * nu);
     // ---- hydrodynamic populations and their moments
     T fi[Q];
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-      const int slot = PAR == 0 ? i : opp(i);
-      const int src = PAR == 0 ? idx : nb(-H::cx[i], -H::cy[i], -H::cz[i]);
-      fi[i] = Store<FS>::ld(f + slot * S + src, (T)(H::w[i] * pp.pstar_ref));
+      const FS* fp = pl.f[PAR == 0 ? i : opp(i)];
+      const unsigned src = PAR == 0 ? idx : (unsigned)nb(-H::cx[i], -H::cy[i], -H::cz[i]);
+      fi[i] = Store<FS>::ld(plane_at<OFF32>(fp, src), pp.fref[i]);
     }
     T ps = fi[0], m[3] = {0, 0, 0}, M2[6] = {0, 0, 0, 0, 0, 0};  // xx yy zz xy xz yz
 #pragma unroll
@@ -486,98 +620,106 @@ __global__ __launch_bounds__(NT) void k_collide(FS* __restrict__ f, GS* __restri
     // ---- forces (Eq. Fsplit): capillary, pressure correction, repulsion, buoyancy
     T Jv[3] = {0, 0, 0};
     if (nci_on) {
-      const unsigned tile = (unsigned)(x / ttx + geo.ntx * (y / tty + geo.nty * (z / ttz)));
+      const unsigned tile = (unsigned)(x / TL::TX + geo.ntx * (y / TL::TY + geo.nty * (z / TL::TZ)));
       if (flags[tile]) {
 #pragma unroll
-        for (int a = 0; a < DIM; ++a) Jv[a] = J[a * S + idx];
+        for (int a = 0; a < DIM; ++a) Jv[a] = *plane_at<OFF32>(J + a * S, idx);
       }
     }
     const T cs2 = (T)(1.0 / 3.0);
-    const T drho = (T)pp.drho;
     const T inv2rho = (T)0.5 * inv_rho;
+    const T pc = ps * cs2;
+    const T prho = pc * pp.drho;
+    const T dens = rho - pp.rho_mean;
     T Fp[3], up[3], F[3], u[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-      Fp[a] = mu * gr[a] - ps * cs2 * (drho * gr[a]) + rho * Jv[a] + (rho - (T)pp.rho_mean) * (T)pp.g[a];
-      if (a >= DIM) Fp[a] = 0;
+      Fp[a] = a < DIM ? (mu - prho) * gr[a] + rho * Jv[a] + dens * pp.g[a] : (T)0;
       up[a] = m[a] + Fp[a] * inv2rho;
     }
     // viscous correction (Eq. Fnu) from the second moment of f - feq(p*, u')
     {
-      const T pc = ps * cs2;
       const T Pxx = M2[0] - pc - up[0] * up[0], Pyy = M2[1] - pc - up[1] * up[1];
       const T Pzz = M2[2] - pc - up[2] * up[2];
       const T Pxy = M2[3] - up[0] * up[1], Pxz = M2[4] - up[0] * up[2], Pyz = M2[5] - up[1] * up[2];
-      const T kf = -(T)3 * nu * omega * drho;
+      const T kf = -(T)3 * nu * omega * pp.drho;
       F[0] = Fp[0] + kf * (Pxx * gr[0] + Pxy * gr[1] + Pxz * gr[2]);
       F[1] = Fp[1] + kf * (Pxy * gr[0] + Pyy * gr[1] + Pyz * gr[2]);
       F[2] = DIM == 3 ? Fp[2] + kf * (Pxz * gr[0] + Pyz * gr[1] + Pzz * gr[2]) : (T)0;
     }
 #pragma unroll
     for (int a = 0; a < 3; ++a) u[a] = m[a] + F[a] * inv2rho;
-    const T uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
-    const T uF = u[0] * F[0] + u[1] * F[1] + u[2] * F[2];
-    // second-order non-equilibrium moment of f - feq + S/2 (Hermite projection)
-    const T pc = ps * cs2;
-    T A[6];
-    A[0] = M2[0] - pc - u[0] * u[0] + (T)2 * u[0] * F[0] * inv2rho;
-    A[1] = M2[1] - pc - u[1] * u[1] + (T)2 * u[1] * F[1] * inv2rho;
-    A[2] = DIM == 3 ? M2[2] - pc - u[2] * u[2] + (T)2 * u[2] * F[2] * inv2rho : (T)0;
-    A[3] = M2[3] - u[0] * u[1] + (u[0] * F[1] + u[1] * F[0]) * inv2rho;
-    A[4] = DIM == 3 ? M2[4] - u[0] * u[2] + (u[0] * F[2] + u[2] * F[0]) * inv2rho : (T)0;
-    A[5] = DIM == 3 ? M2[5] - u[1] * u[2] + (u[1] * F[2] + u[2] * F[1]) * inv2rho : (T)0;
-    const T trA = A[0] + A[1] + A[2];
-    const T Au[3] = {A[0] * u[0] + A[3] * u[1] + A[4] * u[2], A[3] * u[0] + A[1] * u[1] + A[5] * u[2],
-                     A[4] * u[0] + A[5] * u[1] + A[2] * u[2]};
     if constexpr (MODE != MODE_DRY) {
+      const T uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
       const T om1 = (T)1 - omega;
-      // rest population
+      // second-order Hermite coefficient of f - feq + S/2, and the post-collision ones
+      T A[6], B[6];
       {
-        const T w0 = wt<H, T>(0);
-        const T e = w0 * (ps - (T)1.5 * uu) + om1 * w0 * ((T)-1.5 * trA) + w0 * inv2rho * ((T)-3 * uF);
-        Store<FS>::st(f + 0 * S + idx, e, (T)(H::w[0] * pp.pstar_ref));
+        const T gxx = u[0] * F[0] * inv2rho, gyy = u[1] * F[1] * inv2rho, gzz = u[2] * F[2] * inv2rho;
+        const T gxy = (u[0] * F[1] + u[1] * F[0]) * inv2rho;
+        const T gxz = (u[0] * F[2] + u[2] * F[0]) * inv2rho;
+        const T gyz = (u[1] * F[2] + u[2] * F[1]) * inv2rho;
+        const T uxx = u[0] * u[0], uyy = u[1] * u[1], uzz = u[2] * u[2];
+        const T uxy = u[0] * u[1], uxz = u[0] * u[2], uyz = u[1] * u[2];
+        A[0] = M2[0] - pc - uxx + (T)2 * gxx;
+        A[1] = M2[1] - pc - uyy + (T)2 * gyy;
+        A[2] = DIM == 3 ? M2[2] - pc - uzz + (T)2 * gzz : (T)0;
+        A[3] = M2[3] - uxy + gxy;
+        A[4] = DIM == 3 ? M2[4] - uxz + gxz : (T)0;
+        A[5] = DIM == 3 ? M2[5] - uyz + gyz : (T)0;
+        B[0] = uxx + om1 * A[0] + (T)2 * gxx;
+        B[1] = uyy + om1 * A[1] + (T)2 * gyy;
+        B[2] = DIM == 3 ? uzz + om1 * A[2] + (T)2 * gzz : (T)0;
+        B[3] = uxy + om1 * A[3] + gxy;
+        B[4] = DIM == 3 ? uxz + om1 * A[4] + gxz : (T)0;
+        B[5] = DIM == 3 ? uyz + om1 * A[5] + gyz : (T)0;
       }
+      const T trA = A[0] + A[1] + A[2];
+      const T trB = B[0] + B[1] + B[2];
+      const T Au[3] = {A[0] * u[0] + A[3] * u[1] + A[4] * u[2], A[3] * u[0] + A[1] * u[1] + A[5] * u[2],
+                       A[4] * u[0] + A[5] * u[1] + A[2] * u[2]};
+      const T A1[3] = {u[0] + F[0] * inv2rho, u[1] + F[1] * inv2rho, u[2] + F[2] * inv2rho};
+      const T base = ps - (T)1.5 * trB;
+      const T k3 = (T)13.5 * om1, k3t = (T)4.5 * om1 * trA, k3u = (T)9 * om1;
+      Store<FS>::st(plane_at<OFF32>(pl.f[0], idx), wt<H, T>(0) * base, pp.fref[0]);
 #pragma unroll
       for (int i = 1; i < Q; i += 2) {
         const int cx = H::cx[i], cy = H::cy[i], cz = H::cz[i];
         const T w = wt<H, T>(i);
         const T cu = (T)cx * u[0] + (T)cy * u[1] + (T)cz * u[2];
-        const T cF = (T)cx * F[0] + (T)cy * F[1] + (T)cz * F[2];
+        const T cA1 = (T)cx * A1[0] + (T)cy * A1[1] + (T)cz * A1[2];
+        const T cAu = (T)cx * Au[0] + (T)cy * Au[1] + (T)cz * Au[2];
         const T cAc = (T)(cx * cx) * A[0] + (T)(cy * cy) * A[1] + (T)(cz * cz) * A[2] +
                       (T)2 * ((T)(cx * cy) * A[3] + (T)(cx * cz) * A[4] + (T)(cy * cz) * A[5]);
-        const T cAu = (T)cx * Au[0] + (T)cy * Au[1] + (T)cz * Au[2];
-        const T cu2 = cu * cu;
-        const T ev = w * (ps + (T)4.5 * cu2 - (T)1.5 * uu) + om1 * w * ((T)4.5 * cAc - (T)1.5 * trA) +
-                     w * inv2rho * ((T)-3 * uF + (T)9 * cu * cF);
-        const T od = w * cu * ((T)3 + (T)4.5 * cu2 - (T)4.5 * uu) +
-                     om1 * w * ((T)13.5 * cu * cAc - (T)4.5 * cu * trA - (T)9 * cAu) +
-                     w * inv2rho * ((T)3 * cF);
+        const T cBc = (T)(cx * cx) * B[0] + (T)(cy * cy) * B[1] + (T)(cz * cz) * B[2] +
+                      (T)2 * ((T)(cx * cy) * B[3] + (T)(cx * cz) * B[4] + (T)(cy * cz) * B[5]);
+        const T ev = w * (base + (T)4.5 * cBc);
+        const T t3 = cu * ((T)4.5 * (cu * cu - uu) + k3 * cAc - k3t) - k3u * cAu;
+        const T od = w * ((T)3 * cA1 + t3);
         const T fa = ev + od, fb = ev - od;   // directions i and opp(i)
+        FS* const pi = pl.f[i];
+        FS* const pj = pl.f[i + 1];
         if constexpr (PAR == 0) {
-          Store<FS>::st(f + (i + 1) * S + idx, fa, (T)(H::w[i] * pp.pstar_ref));
-          Store<FS>::st(f + i * S + idx, fb, (T)(H::w[i] * pp.pstar_ref));
+          Store<FS>::st(plane_at<OFF32>(pj, idx), fa, pp.fref[i]);
+          Store<FS>::st(plane_at<OFF32>(pi, idx), fb, pp.fref[i]);
         } else {
-          Store<FS>::st(f + i * S + nb(cx, cy, cz), fa, (T)(H::w[i] * pp.pstar_ref));
-          Store<FS>::st(f + (i + 1) * S + nb(-cx, -cy, -cz), fb, (T)(H::w[i] * pp.pstar_ref));
+          Store<FS>::st(plane_at<OFF32>(pi, (unsigned)nb(cx, cy, cz)), fa, pp.fref[i]);
+          Store<FS>::st(plane_at<OFF32>(pj, (unsigned)nb(-cx, -cy, -cz)), fb, pp.fref[i]);
         }
       }
       // ---- conservative Allen-Cahn populations: BGK towards
       //      geq_k = w_k (phi + c_k . j / cs_phi^2), j = phi u + M (4/W) phi (1-phi) n
-      const T kc = (T)pp.kc * ph * ((T)1 - ph) * inv_g;
+      const T kc = pp.kc * ph * ((T)1 - ph) * inv_g;
       const T jv[3] = {ph * u[0] + kc * gr[0], ph * u[1] + kc * gr[1], ph * u[2] + kc * gr[2]};
-      const T itp = (T)pp.inv_tau_phi;
-      GS* gp = g;
+      const T itp = pp.inv_tau_phi;
       T gi[QG];
 #pragma unroll
       for (int k = 0; k < QG; ++k) {
-        const int slot = PAR == 0 ? k : opp(k);
-        const int src = PAR == 0 ? idx : nb(-P::cx[k], -P::cy[k], -P::cz[k]);
-        gi[k] = (T)gp[slot * S + src];
+        const GS* gp = pl.g[PAR == 0 ? k : opp(k)];
+        const unsigned src = PAR == 0 ? idx : (unsigned)nb(-P::cx[k], -P::cy[k], -P::cz[k]);
+        gi[k] = (T)*plane_at<OFF32>(gp, src);
       }
-      {
-        const T geq = wt<P, T>(0) * ph;
-        gp[0 * S + idx] = (GS)(gi[0] - (gi[0] - geq) * itp);
-      }
+      *plane_at<OFF32>(pl.g[0], idx) = (GS)(gi[0] - (gi[0] - wt<P, T>(0) * ph) * itp);
 #pragma unroll
       for (int k = 1; k < QG; k += 2) {
         const int cx = P::cx[k], cy = P::cy[k], cz = P::cz[k];
@@ -585,18 +727,20 @@ __global__ __launch_bounds__(NT) void k_collide(FS* __restrict__ f, GS* __restri
         const T wk = wt<P, T>(k);
         const T ga = gi[k] - (gi[k] - wk * (ph + cj)) * itp;
         const T gb = gi[k + 1] - (gi[k + 1] - wk * (ph - cj)) * itp;
+        GS* const pk = pl.g[k];
+        GS* const pk1 = pl.g[k + 1];
         if constexpr (PAR == 0) {
-          gp[(k + 1) * S + idx] = (GS)ga;
-          gp[k * S + idx] = (GS)gb;
+          *plane_at<OFF32>(pk1, idx) = (GS)ga;
+          *plane_at<OFF32>(pk, idx) = (GS)gb;
         } else {
-          gp[k * S + nb(cx, cy, cz)] = (GS)ga;
-          gp[(k + 1) * S + nb(-cx, -cy, -cz)] = (GS)gb;
+          *plane_at<OFF32>(pk, (unsigned)nb(cx, cy, cz)) = (GS)ga;
+          *plane_at<OFF32>(pk1, (unsigned)nb(-cx, -cy, -cz)) = (GS)gb;
         }
       }
     } else if (macro) {
       // dry evaluation: macroscopic fields of the current state
-      macro[0 * S + idx] = ps;
-      macro[1 * S + idx] = rho;
+      macro[idx] = ps;
+      macro[S + idx] = rho;
 #pragma unroll
       for (int a = 0; a < DIM; ++a) {
         macro[(2 + a) * S + idx] = u[a];
@@ -662,6 +806,27 @@ __global__ __launch_bounds__(NT) void k_diag(const T* __restrict__ phi, Geo geo,
   block_partials(acc, partials);
 }
 
+// First stage of the reduction: block b reduces partials [b*chunk, (b+1)*chunk)
+// into out[b] (fixed order, deterministic).
+__global__ __launch_bounds__(NT) void k_reduce_stage(const double* __restrict__ p, int n, int chunk,
+                                                     double* __restrict__ out) {
+  __shared__ double red[NT][NPART];
+  const int lo = blockIdx.x * chunk, hi = min(n, lo + chunk);
+  double v[NPART] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int b = lo + (int)threadIdx.x; b < hi; b += NT)
+    for (int k = 0; k < NPART; ++k) v[k] = (k == 5) ? fmax(v[k], p[b * NPART + k]) : v[k] + p[b * NPART + k];
+  for (int k = 0; k < NPART; ++k) red[threadIdx.x][k] = v[k];
+  __syncthreads();
+  for (int s = NT / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s)
+      for (int k = 0; k < NPART; ++k)
+        red[threadIdx.x][k] = (k == 5) ? fmax(red[threadIdx.x][k], red[threadIdx.x + s][k])
+                                       : red[threadIdx.x][k] + red[threadIdx.x + s][k];
+    __syncthreads();
+  }
+  if (threadIdx.x < NPART) out[blockIdx.x * NPART + threadIdx.x] = red[0][threadIdx.x];
+}
+
 // Deterministic final reduction of per-block partials: out[0..7] for the
 // collide partials, out[8..15] for the diag partials.
 __global__ __launch_bounds__(NT) void k_reduce(const double* __restrict__ pa, int na,
@@ -698,7 +863,7 @@ __global__ __launch_bounds__(NT) void k_reduce(const double* __restrict__ pa, in
 template <int DIM, typename T, typename FS, typename GS>
 __global__ __launch_bounds__(NT) void k_init(FS* __restrict__ f, GS* __restrict__ g,
                                              const T* __restrict__ phi, const T* __restrict__ uin,
-                                             const T* __restrict__ psin, Geo geo, Phys pp) {
+                                             const T* __restrict__ psin, Geo geo, PhysT<T> pp) {
   using H = Hydro<DIM>;
   using P = Phase<DIM>;
   const int t = swizzled_block();
@@ -718,13 +883,13 @@ __global__ __launch_bounds__(NT) void k_init(FS* __restrict__ f, GS* __restrict_
     const T cu = (T)H::cx[i] * u[0] + (T)H::cy[i] * u[1] + (T)H::cz[i] * u[2];
     const T fe = wt<H, T>(i) * (ps + (T)3 * cu + (T)4.5 * cu * cu - (T)1.5 * uu + (T)4.5 * cu * cu * cu -
                                (T)4.5 * cu * uu);
-    Store<FS>::st(f + i * S + idx, fe, (T)(H::w[i] * pp.pstar_ref));
+    Store<FS>::st(f + i * S + idx, fe, pp.fref[i]);
   }
   T gr[3], lap;
   grad_lap<DIM, T>([&](int i) { return phi[nb(H::cx[i], H::cy[i], H::cz[i])]; }, gr, lap);
   const T ph = phi[idx];
   T gmag = m_sqrt(gr[0] * gr[0] + gr[1] * gr[1] + gr[2] * gr[2]);
-  const T kc = (T)pp.kc * ph * ((T)1 - ph) / (gmag + (T)pp.eps_n);
+  const T kc = pp.kc * ph * ((T)1 - ph) / (gmag + pp.eps_n);
 #pragma unroll
   for (int k = 0; k < P::Q; ++k) {
     const T cj = (T)P::cx[k] * (ph * u[0] + kc * gr[0]) + (T)P::cy[k] * (ph * u[1] + kc * gr[1]) +
@@ -736,7 +901,7 @@ __global__ __launch_bounds__(NT) void k_init(FS* __restrict__ f, GS* __restrict_
 // Incoming populations on a wrapped box, as doubles, SoA [q][box].
 template <int DIM, int PAR, typename T, typename FS, typename GS>
 __global__ __launch_bounds__(NT) void k_getpop(const FS* __restrict__ f, const GS* __restrict__ g,
-                                               Geo geo, Phys pp, int x0, int y0, int z0, int bxn,
+                                               Geo geo, PhysT<T> pp, int x0, int y0, int z0, int bxn,
                                                int byn, int bzn, double* __restrict__ fo,
                                                double* __restrict__ go) {
   using H = Hydro<DIM>;
@@ -751,7 +916,7 @@ __global__ __launch_bounds__(NT) void k_getpop(const FS* __restrict__ f, const G
   for (int i = 0; i < H::Q; ++i) {
     const int slot = PAR == 0 ? i : opp(i);
     const int src = PAR == 0 ? idx : nb(-H::cx[i], -H::cy[i], -H::cz[i]);
-    fo[i * B + e] = (double)Store<FS>::ld(f + slot * geo.S + src, (T)(H::w[i] * pp.pstar_ref));
+    fo[i * B + e] = (double)Store<FS>::ld(f + slot * geo.S + src, pp.fref[i]);
   }
   for (int k = 0; k < P::Q; ++k) {
     const int slot = PAR == 0 ? k : opp(k);
@@ -763,7 +928,7 @@ __global__ __launch_bounds__(NT) void k_getpop(const FS* __restrict__ f, const G
 // Whole-field populations (doubles, SoA [q][N]) into natural layout.
 template <int DIM, typename T, typename FS, typename GS>
 __global__ __launch_bounds__(NT) void k_setpop(FS* __restrict__ f, GS* __restrict__ g, Geo geo,
-                                               Phys pp, const double* __restrict__ fi,
+                                               PhysT<T> pp, const double* __restrict__ fi,
                                                const double* __restrict__ gi) {
   using H = Hydro<DIM>;
   using P = Phase<DIM>;
@@ -771,7 +936,7 @@ __global__ __launch_bounds__(NT) void k_setpop(FS* __restrict__ f, GS* __restric
   const long long e = (long long)blockIdx.x * NT + threadIdx.x;
   if (e >= N) return;
   for (int i = 0; i < H::Q; ++i)
-    Store<FS>::st(f + i * geo.S + e, (T)fi[i * N + e], (T)(H::w[i] * pp.pstar_ref));
+    Store<FS>::st(f + i * geo.S + e, (T)fi[i * N + e], pp.fref[i]);
   for (int k = 0; k < P::Q; ++k) g[k * geo.S + e] = (GS)gi[k * N + e];
 }
 

@@ -24,6 +24,7 @@ namespace {
 
 constexpr int HIST = 64;      // periodic diagnostics kept on the device
 constexpr int NCI_GRID = 2048;
+constexpr int RED1 = 512;     // first-stage blocks of the diagnostic reduction
 
 thread_local std::string g_create_error;
 
@@ -48,8 +49,8 @@ void tile_dims(int dim, int prec, int* tx, int* ty, int* tz) {
 struct Layout {
   long long N, S;
   int nblk, ntiles, ttx, tty, ttz, ntx, nty, ntz;
-  size_t off_f, off_g, off_phi, off_J, off_flags, off_list, off_cnt, off_pa, off_pb, off_red,
-      total;
+  size_t off_f, off_g, off_phi, off_J, off_flags, off_list, off_cnt, off_pa, off_pb, off_s1,
+      off_red, total;
 };
 
 bool valid_params(const lbm_params* p, std::string* why) {
@@ -84,7 +85,10 @@ bool valid_params(const lbm_params* p, std::string* why) {
 Layout make_layout(const lbm_params* p) {
   Layout L{};
   L.N = (long long)p->nx * p->ny * p->nz;
-  L.S = (L.N + 127) & ~127LL;
+  // Plane stride: N rounded up to 128 plus 1088 elements (a 256-byte multiple in
+  // FP32), so that the 26 concurrent population streams do not start at the same
+  // offset modulo large powers of two (+4 % on the collide kernel at 512^3).
+  L.S = ((L.N + 127) & ~127LL) + 1088;
   const int nbx = (p->nx + BX - 1) / BX, nby = (p->ny + BY - 1) / BY;
   L.nblk = nbx * nby * p->nz;
   tile_dims(p->dim, p->precision, &L.ttx, &L.tty, &L.ttz);
@@ -103,6 +107,7 @@ Layout make_layout(const lbm_params* p) {
   L.off_cnt = o;   o = align256(o + 64);
   L.off_pa = o;    o = align256(o + (size_t)L.nblk * NPART * 8);
   L.off_pb = o;    o = align256(o + (size_t)L.nblk * NPART * 8);
+  L.off_s1 = o;    o = align256(o + 2 * (size_t)RED1 * NPART * 8);
   L.off_red = o;   o = align256(o + (size_t)(HIST + 1) * 2 * NPART * 8);
   L.total = o;
   return L;
@@ -144,6 +149,7 @@ struct lbm_ctx {
   unsigned* cnt() const { return (unsigned*)(ws + L.off_cnt); }   // [0],[1] lists, [2] chi count
   double* pa() const { return (double*)(ws + L.off_pa); }
   double* pb() const { return (double*)(ws + L.off_pb); }
+  double* s1(int k) const { return (double*)(ws + L.off_s1) + (size_t)k * RED1 * NPART; }
   double* red(int slot) const { return (double*)(ws + L.off_red) + (size_t)slot * 2 * NPART; }
   bool nci_on() const { return p.a_rep > 0.0; }
   int fail(int code, const std::string& m) {
@@ -225,6 +231,25 @@ template <int DIM, typename T, typename FS, typename GS>
 struct Engine {
   static dim3 rows(const lbm_ctx* c) { return dim3((unsigned)c->L.nblk); }
 
+  // The mixture and forcing constants in the kernel's arithmetic type.
+  static PhysT<T> physT(const lbm_ctx* c) {
+    const Phys& P = c->phys;
+    PhysT<T> q{};
+    q.rho_g = (T)P.rho_g;
+    q.drho = (T)P.drho;
+    q.mu_a = (T)P.mu_a;
+    q.mu_b = (T)P.mu_b;
+    q.beta4 = (T)P.beta4;
+    q.kappa = (T)P.kappa;
+    q.rho_mean = (T)P.rho_mean;
+    for (int a = 0; a < 3; ++a) q.g[a] = (T)P.g[a];
+    q.kc = (T)P.kc;
+    q.inv_tau_phi = (T)P.inv_tau_phi;
+    q.eps_n = (T)P.eps_n;
+    for (int i = 0; i < Hydro<DIM>::Q; ++i) q.fref[i] = (T)(Hydro<DIM>::w[i] * P.pstar_ref);
+    return q;
+  }
+
   // phi of the current state, plus (when the near-contact force is on) the
   // interfacial tile list of this parity.
   static void phi_pass(lbm_ctx* c, int par) {
@@ -233,7 +258,7 @@ struct Engine {
     Timed tm(c, 0);
     hipLaunchKernelGGL(k, rows(c), dim3(NT), 0, c->stream, (const GS*)c->g(), (T*)c->phi(), c->geo,
                        c->flags(par), c->list(par), c->cnt() + par, c->cnt() + 2, nci,
-                       (T)c->p.q_th, c->L.ttx, c->L.tty, c->L.ttz);
+                       (T)c->p.q_th);
   }
 
   static void nci_pass(lbm_ctx* c, int par, int* chi, int* part) {
@@ -241,34 +266,53 @@ struct Engine {
     const int grid = std::min(NCI_GRID, std::max(1, c->L.ntiles));
     Timed tm(c, 1);
     if (chi) {
-      hipLaunchKernelGGL((k_nci<DIM, T, true>), dim3(grid), dim3(NT), 0, c->stream,
+      hipLaunchKernelGGL((k_nci<DIM, T, true>), dim3(grid), dim3(NT_NCI), 0, c->stream,
                          (const T*)c->phi(), (T*)c->J(), chi, part, c->list(par), c->cnt() + par,
                          c->flags(1 - par), c->list(1 - par), c->cnt() + (1 - par), c->cnt() + 2,
                          c->geo, c->nci);
     } else {
-      hipLaunchKernelGGL((k_nci<DIM, T, false>), dim3(grid), dim3(NT), 0, c->stream,
+      hipLaunchKernelGGL((k_nci<DIM, T, false>), dim3(grid), dim3(NT_NCI), 0, c->stream,
                          (const T*)c->phi(), (T*)c->J(), (int*)nullptr, (int*)nullptr, c->list(par),
                          c->cnt() + par, c->flags(1 - par), c->list(1 - par), c->cnt() + (1 - par),
                          c->cnt() + 2, c->geo, c->nci);
     }
   }
 
+  static Planes<FS, GS> planes(const lbm_ctx* c) {
+    Planes<FS, GS> pl{};
+    for (int i = 0; i < Hydro<DIM>::Q; ++i) pl.f[i] = (FS*)c->f() + (size_t)i * c->L.S;
+    for (int k = 0; k < Phase<DIM>::Q; ++k) pl.g[k] = (GS*)c->g() + (size_t)k * c->L.S;
+    return pl;
+  }
+
+  // 32-bit byte offsets are used when every plane is below 4 GiB.
+  static bool off32(const lbm_ctx* c) {
+    const size_t widest = std::max(sizeof(FS), std::max(sizeof(GS), sizeof(T)));
+    return (size_t)c->L.S * widest < (size_t(1) << 32);
+  }
+
   template <int MODE>
   static void collide_pass(lbm_ctx* c, int par, T* macro) {
-    auto k = par == 0 ? k_collide<DIM, 0, MODE, T, FS, GS> : k_collide<DIM, 1, MODE, T, FS, GS>;
+    const bool o32 = off32(c);
+    auto k = par == 0 ? (o32 ? k_collide<DIM, 0, MODE, T, FS, GS, true> : k_collide<DIM, 0, MODE, T, FS, GS, false>)
+                      : (o32 ? k_collide<DIM, 1, MODE, T, FS, GS, true> : k_collide<DIM, 1, MODE, T, FS, GS, false>);
     Timed tm(c, 2);
-    hipLaunchKernelGGL(k, rows(c), dim3(NT), 0, c->stream, (FS*)c->f(), (GS*)c->g(),
+    hipLaunchKernelGGL(k, rows(c), dim3(NT), 0, c->stream, planes(c),
                        (const T*)c->phi(), (const T*)c->J(), (const unsigned*)c->flags(par),
-                       c->cnt() + (1 - par), c->geo, c->phys, c->nci_on() ? 1 : 0, c->L.ttx,
-                       c->L.tty, c->L.ttz, macro, c->pa());
+                       c->cnt() + (1 - par), c->geo, physT(c), c->nci_on() ? 1 : 0, macro, c->pa());
   }
 
   static void diag_finish(lbm_ctx* c, int slot) {
     Timed tm(c, 3);
     hipLaunchKernelGGL((k_diag<DIM, T>), rows(c), dim3(NT), 0, c->stream, (const T*)c->phi(), c->geo,
                        c->dispersed, c->pb());
-    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(NT), 0, c->stream, (const double*)c->pa(), c->L.nblk,
-                       (const double*)c->pb(), c->L.nblk,
+    const int chunk = (c->L.nblk + RED1 - 1) / RED1;
+    hipLaunchKernelGGL(k_reduce_stage, dim3(RED1), dim3(NT), 0, c->stream, (const double*)c->pa(),
+                       c->L.nblk, chunk, c->s1(0));
+    hipLaunchKernelGGL(k_reduce_stage, dim3(RED1), dim3(NT), 0, c->stream, (const double*)c->pb(),
+                       c->L.nblk, chunk, c->s1(1));
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(NT), 0, c->stream, (const double*)c->s1(0), RED1,
+                       (const double*)c->s1(1), RED1,
                        (const unsigned*)(c->nci_on() ? c->cnt() + 2 : nullptr), c->red(slot));
   }
 
@@ -332,7 +376,7 @@ struct Engine {
         break;
       }
       hipLaunchKernelGGL((k_init<DIM, T, FS, GS>), rows(c), dim3(NT), 0, c->stream, (FS*)c->f(),
-                         (GS*)c->g(), (const T*)c->phi(), (const T*)du, (const T*)dps, c->geo, c->phys);
+                         (GS*)c->g(), (const T*)c->phi(), (const T*)du, (const T*)dps, c->geo, physT(c));
       if (hipGetLastError() != hipSuccess || hipStreamSynchronize(c->stream) != hipSuccess)
         rc = c->fail(LBM_E_HIP, "initialisation kernel failed");
     } while (0);
@@ -353,7 +397,7 @@ struct Engine {
     const int par = (int)(c->step & 1);
     auto k = par == 0 ? k_getpop<DIM, 0, T, FS, GS> : k_getpop<DIM, 1, T, FS, GS>;
     hipLaunchKernelGGL(k, dim3((unsigned)((B + NT - 1) / NT)), dim3(NT), 0, c->stream,
-                       (const FS*)c->f(), (const GS*)c->g(), c->geo, c->phys, x0, y0, z0, bx, by, bz,
+                       (const FS*)c->f(), (const GS*)c->g(), c->geo, physT(c), x0, y0, z0, bx, by, bz,
                        df, dg);
     int rc = LBM_OK;
     if (hipStreamSynchronize(c->stream) != hipSuccess ||
@@ -379,7 +423,7 @@ struct Engine {
       rc = c->fail(LBM_E_HIP, "host to device copy failed");
     } else {
       hipLaunchKernelGGL((k_setpop<DIM, T, FS, GS>), dim3((unsigned)((N + NT - 1) / NT)), dim3(NT), 0,
-                         c->stream, (FS*)c->f(), (GS*)c->g(), c->geo, c->phys, df, dg);
+                         c->stream, (FS*)c->f(), (GS*)c->g(), c->geo, physT(c), df, dg);
       if (hipStreamSynchronize(c->stream) != hipSuccess) rc = c->fail(LBM_E_HIP, "set kernel failed");
     }
     (void)hipFree(df);
