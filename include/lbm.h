@@ -91,9 +91,9 @@ typedef struct {
   double momentum[3];        /* sum rho u                                                   */
   double kinetic_energy;     /* sum rho |u|^2 / 2                                           */
   double max_speed;          /* max |u|                                                     */
-  long n_droplets;           /* Euler characteristic of the dispersed set (8-/26-connected
-                                closed-voxel union): the droplet / bubble count while each
-                                one is simply connected                                    */
+  long n_droplets;           /* connected components of the dispersed set {phi > 1/2}
+                                (droplets) or {phi < 1/2} (bubbles), 8-/26-connected on
+                                the periodic lattice, by union-find on the device       */
   long nci_active;           /* number of cells with chi_nc = 1                             */
   int finite;                /* 1 if every p*, u and phi is finite                          */
 } lbm_diag;
@@ -174,12 +174,22 @@ size_t lbm_state_bytes(const lbm_ctx* ctx);
 int lbm_save_state(lbm_ctx* ctx, void* host_buf, size_t bytes);
 int lbm_load_state(lbm_ctx* ctx, const void* host_buf, size_t bytes);
 
-/* Serving: advance every context by n steps with multi-domain launches that
- * cover all of them at once (kernels loop over a device job table), replayed
- * from a cached HIP graph.  All contexts must live on the same device, share
- * dimension and precision, and be initialised.  Their results equal those of
- * lbm_step on each alone.  Enqueued on the first context's stream; the others'
- * streams are synchronised first.  Asynchronous. */
+/* Serving: advance every context by n steps of the coupled update (Sec. 2,
+ * the step lbm_step performs) with multi-domain launches that cover all of
+ * them at once: one grid spans the blocks of every lattice and each block finds
+ * its lattice in a device job table.  Whole groups of 8 steps replay a HIP
+ * graph captured on the first call for this ordered set of contexts (cached,
+ * at most 8 sets; lbm_destroy drops the sets that hold a context); the
+ * remaining n % 8 steps are launched directly.  All contexts must live on the
+ * same device, share dimension and precision, be initialised and appear once.
+ * Their populations after the call equal bit for bit those of lbm_step on each
+ * alone; periodic diagnostics (diag_interval) are not taken inside a batch.
+ * Enqueued on the first context's stream after the others' streams have been
+ * synchronised; later work on every context's stream waits for it.
+ * Asynchronous.  Errors: LBM_E_INVALID for a bad list, LBM_E_STATE for an
+ * uninitialised context, LBM_E_OOM / LBM_E_HIP from allocation or launch, with
+ * the message on the first context.  Calls on overlapping sets of contexts
+ * from several host threads at once are not supported. */
 int lbm_batch_step(lbm_ctx* const* ctxs, int count, int n);
 
 #ifdef __cplusplus

@@ -1,7 +1,9 @@
 """Build the gfx950 shared library paper_2603_17481_amd/liblbm.so from csrc/.
 
 hipcc cross-compiles for gfx950 without a GPU.  Packed FP32 instructions are
-disabled for all device code (-packed-fp32-ops).
+disabled for all device code (-packed-fp32-ops), and so is floating-point
+contraction (the kernels' arithmetic is exactly the source's, in every kernel
+that runs it).
 """
 import os
 import subprocess
@@ -17,6 +19,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-ffp-contract=off",
     "-Wall", "-Wno-unused-function",
     "-I" + os.path.join(ROOT, "include"),
 ]

@@ -8,9 +8,15 @@
 //              the repulsive flux J (Sec. 2.3) written for every cell of the tile.
 //   k_collide  fused hydrodynamic + phase-field collide and stream, in place,
 //              structure-of-arrays; reads J only in flagged tiles.
-//   k_diag     FP64 sums of phi and the Euler characteristic of the dispersed set.
+//   k_diag     FP64 sums of phi and the droplet count (k_cc_init / k_cc_merge:
+//              union-find labels of the dispersed set).
 // Grids are 1-D with an XCD-aware block swizzle: consecutive tiles of the domain
 // land on the same XCD so that stencil re-reads hit its L2.
+//
+// Floating-point contraction is off for all of this code: every kernel that
+// runs the per-cell update (single lattice, batch of lattices, with or without
+// diagnostics) then evaluates exactly the operations written here in the same
+// order, so a lattice's state does not depend on which kernel advanced it.
 #pragma once
 
 #include <hip/hip_bf16.h>
@@ -18,6 +24,8 @@
 #include <hip/hip_runtime.h>
 
 #include "lattice.hpp"
+
+#pragma clang fp contract(off)
 
 namespace lbm {
 
@@ -150,6 +158,37 @@ struct Nbr {
   }
 };
 
+// s . v for a lattice vector s whose components are -1, 0 or 1 and known at
+// compile time once the direction loops are unrolled: the nonzero terms are
+// added with their signs, so no product by 0 or +-1 is evaluated.
+template <typename T>
+__device__ __forceinline__ T sdot(int sx, int sy, int sz, T vx, T vy, T vz) {
+  T acc = (T)0;
+  bool any = false;
+  auto add = [&](int sg, T v) {
+    if (!sg) return;
+    acc = any ? (sg > 0 ? acc + v : acc - v) : (sg > 0 ? v : -v);
+    any = true;
+  };
+  add(sx, vx);
+  add(sy, vy);
+  add(sz, vz);
+  return acc;
+}
+
+// a * b + c with one rounding (an explicit fused multiply-add; nothing is fused
+// implicitly in this code).
+__device__ __forceinline__ float fmad(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmad(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// c c : A for a symmetric tensor stored as (xx yy zz xy xz yz).
+template <typename T>
+__device__ __forceinline__ T ccdot(int cx, int cy, int cz, const T A[6]) {
+  const T d = sdot(cx * cx, cy * cy, cz * cz, A[0], A[1], A[2]);
+  if (cx * cy == 0 && cx * cz == 0 && cy * cz == 0) return d;
+  return d + (T)2 * sdot(cx * cy, cx * cz, cy * cz, A[3], A[4], A[5]);
+}
+
 // Isotropic gradient and Laplacian with the hydrodynamic lattice weights
 // (Eqs. grad_iso, lap_iso; 1/cs^2 = 3).  get(i) returns psi(x + c_i).
 template <int DIM, typename T, typename G>
@@ -192,21 +231,17 @@ __device__ __forceinline__ T wave_max(T v) {
 // (a1) phi moment of the phase-field populations
 // ---------------------------------------------------------------------------
 
+// phi of one cell from its incoming phase-field populations (AA parity PAR),
+// accumulated in FP64 (exact for FP32 populations) and rounded once; an
+// interfacial cell flags and lists its near-contact tile.
 template <int DIM, int PAR, typename T, typename GS>
-__global__ __launch_bounds__(NT) void k_phi(const GS* __restrict__ g, T* __restrict__ phi, Geo geo,
-                                            unsigned* __restrict__ flags,
-                                            unsigned* __restrict__ list,
-                                            unsigned* __restrict__ cnt,
-                                            unsigned* __restrict__ nci_count, int nci_on, T q_th) {
+__device__ __forceinline__ void phi_cell(const GS* __restrict__ g, T* __restrict__ phi, const Geo& geo,
+                                         unsigned* __restrict__ flags, unsigned* __restrict__ list,
+                                         unsigned* __restrict__ cnt, int nci_on, T q_th, int x, int y,
+                                         int z) {
   using P = Phase<DIM>;
   using TL = NciTile<DIM, T>;
-  if (nci_on && blockIdx.x == 0 && threadIdx.x == 0) *nci_count = 0u;
-  const int t = swizzled_block();
-  const int bx = t % geo.nbx, r = t / geo.nbx, by = r % geo.nby, z = r / geo.nby;
-  const int x = bx * BX + (int)(threadIdx.x & (BX - 1)), y = by * BY + (int)(threadIdx.x / BX);
-  if (x >= geo.nx || y >= geo.ny) return;
   const int idx = x + geo.nx * (y + geo.ny * z);
-  // accumulated in FP64 (exact for FP32 populations), rounded once
   double acc = 0.0;
   if constexpr (PAR == 0) {
 #pragma unroll
@@ -226,6 +261,27 @@ __global__ __launch_bounds__(NT) void k_phi(const GS* __restrict__ g, T* __restr
       if (flags[tile] == 0u && atomicExch(&flags[tile], 1u) == 0u) list[atomicAdd(cnt, 1u)] = tile;
     }
   }
+}
+
+// Cell of thread: block t of a domain covers BX x BY cells of one z plane.
+__device__ __forceinline__ void block_cell(int t, const Geo& geo, int& x, int& y, int& z) {
+  const int bx = t % geo.nbx, r = t / geo.nbx, by = r % geo.nby;
+  z = r / geo.nby;
+  x = bx * BX + (int)(threadIdx.x & (BX - 1));
+  y = by * BY + (int)(threadIdx.x / BX);
+}
+
+template <int DIM, int PAR, typename T, typename GS>
+__global__ __launch_bounds__(NT) void k_phi(const GS* __restrict__ g, T* __restrict__ phi, Geo geo,
+                                            unsigned* __restrict__ flags,
+                                            unsigned* __restrict__ list,
+                                            unsigned* __restrict__ cnt,
+                                            unsigned* __restrict__ nci_count, int nci_on, T q_th) {
+  if (nci_on && blockIdx.x == 0 && threadIdx.x == 0) *nci_count = 0u;
+  int x, y, z;
+  block_cell(swizzled_block(), geo, x, y, z);
+  if (x >= geo.nx || y >= geo.ny) return;
+  phi_cell<DIM, PAR, T, GS>(g, phi, geo, flags, list, cnt, nci_on, q_th, x, y, z);
 }
 
 // ---------------------------------------------------------------------------
@@ -260,245 +316,272 @@ __device__ __forceinline__ void group_min(int& d2, T& dot) {
 // first candidate in scan order within tie_eps of that dot; the planes are
 // combined with wave shuffles; (5) the group leader builds J (Sec. 2.3.3) and
 // the tile's J is written from LDS, zero for cells without a partner.
+template <int DIM, typename T>
+struct NciShared {
+  using TL = NciTile<DIM, T>;
+  static constexpr int TX = TL::TX, TY = TL::TY, TZ = TL::TZ, TC = TX * TY * TZ;
+  static constexpr int PX = TX + 2 * PHI_HALO, PY = TY + 2 * PHI_HALO, PZ = DIM == 3 ? TZ + 2 * PHI_HALO : 1;
+  static constexpr int NX = TX + 2 * NQ_HALO, NY = TY + 2 * NQ_HALO, NZ = DIM == 3 ? TZ + 2 * NQ_HALO : 1;
+  static constexpr int NPH = PX * PY * PZ, NNQ = NX * NY * NZ;
+  T phs[NPH];
+  T nqs[DIM + 1][NNQ];
+  short glist[TC];   // gated tile cells
+  short gslot[TC];   // tile cell -> index in glist, or -1
+  T gJ[TC][DIM];     // result per gated cell
+  int gpart[TC];     // packed partner offset + 1 (0: no partner)
+  int ng;
+};
+
+// Clears the tile flags of the other AA parity (set by the previous step) so
+// that the next step's phi pass starts from empty flags.
+__device__ __forceinline__ void nci_clear_other(unsigned* __restrict__ flags_other,
+                                                const unsigned* __restrict__ list_other,
+                                                const unsigned* __restrict__ cnt_other) {
+  const unsigned nother = *cnt_other;
+  for (unsigned k = blockIdx.x * NT_NCI + threadIdx.x; k < nother; k += gridDim.x * NT_NCI)
+    flags_other[list_other[k]] = 0u;
+}
+
+// Per listed tile: (1) phi with a halo of 4 into LDS; (2) q on tile + 3 and
+// n only where q >= q_th (n is read only after a candidate passes the gate);
+// (3) the gated cells of the tile are listed; (4) each gated cell gets an
+// 8-lane group whose lanes scan one window plane each (dz in 3D, dy in 2D):
+// pass 0 finds the smallest |r|^2 and the smallest n(x).n(y) at it, pass 1 the
+// first candidate in scan order within tie_eps of that dot; the planes are
+// combined with wave shuffles; (5) the group leader builds J (Sec. 2.3.3) and
+// the tile's J is written from LDS, zero for cells without a partner.
 template <int DIM, typename T, bool DEBUG>
-__global__ __launch_bounds__(NT_NCI) void k_nci(const T* __restrict__ phi, T* __restrict__ J,
-                                            int* __restrict__ chi_out, int* __restrict__ part_out,
-                                            const unsigned* __restrict__ list,
-                                            const unsigned* __restrict__ cnt,
-                                            unsigned* __restrict__ flags_other,
-                                            const unsigned* __restrict__ list_other,
-                                            const unsigned* __restrict__ cnt_other,
-                                            unsigned* __restrict__ nci_count, Geo geo, NciP np) {
+__device__ __forceinline__ void nci_tile(NciShared<DIM, T>& sm, unsigned t, const T* __restrict__ phi,
+                                         T* __restrict__ J, int* __restrict__ chi_out,
+                                         int* __restrict__ part_out, const Geo& geo, const NciP& np,
+                                         unsigned& my_active) {
   using TL = NciTile<DIM, T>;
   using L = Hydro<DIM>;
   constexpr int TX = TL::TX, TY = TL::TY, TZ = TL::TZ;
   constexpr int TC = TX * TY * TZ;
-  constexpr int PX = TX + 2 * PHI_HALO, PY = TY + 2 * PHI_HALO, PZ = DIM == 3 ? TZ + 2 * PHI_HALO : 1;
-  constexpr int NX = TX + 2 * NQ_HALO, NY = TY + 2 * NQ_HALO, NZ = DIM == 3 ? TZ + 2 * NQ_HALO : 1;
-  constexpr int NPH = PX * PY * PZ, NNQ = NX * NY * NZ;
-  __shared__ T phs[NPH];
-  __shared__ T nqs[DIM + 1][NNQ];
-  __shared__ short glist[TC];          // gated tile cells
-  __shared__ short gslot[TC];          // tile cell -> index in glist, or -1
-  __shared__ T gJ[TC][DIM];            // result per gated cell
-  __shared__ int gpart[TC];            // packed partner offset + 1 (0: no partner)
-  __shared__ int s_ng;
-
-  // Flags of the previous step's parity are cleared here, before the next
-  // step's phi kernel sets them again.
-  {
-    const unsigned nother = *cnt_other;
-    for (unsigned k = blockIdx.x * NT_NCI + threadIdx.x; k < nother; k += gridDim.x * NT_NCI)
-      flags_other[list_other[k]] = 0u;
-  }
-  const unsigned ntiles = *cnt;
+  constexpr int PX = NciShared<DIM, T>::PX, PY = NciShared<DIM, T>::PY;
+  constexpr int NX = NciShared<DIM, T>::NX, NY = NciShared<DIM, T>::NY;
+  constexpr int NPH = NciShared<DIM, T>::NPH, NNQ = NciShared<DIM, T>::NNQ;
   const T q_th = (T)np.q_th, eta = (T)np.eta, cos_opp = (T)np.cos_opp, eps_n = (T)np.eps_n,
           eps_q = (T)np.eps_q, tie = (T)np.tie_eps;
   const int w = np.w;
   const int lane8 = threadIdx.x & 7, grp = threadIdx.x >> 3;
   constexpr int NGRP = NT_NCI / 8;
-  unsigned my_active = 0;
-  for (unsigned k = blockIdx.x; k < ntiles; k += gridDim.x) {
-    const unsigned t = list[k];
-    const int tx = (int)(t % (unsigned)geo.ntx);
-    const int ty = (int)((t / (unsigned)geo.ntx) % (unsigned)geo.nty);
-    const int tz = (int)(t / ((unsigned)geo.ntx * (unsigned)geo.nty));
-    const int ox = tx * TX, oy = ty * TY, oz = tz * TZ;
-    if (threadIdx.x == 0) s_ng = 0;
-    // (1) phi tile with halo
-    for (int e = threadIdx.x; e < NPH; e += NT_NCI) {
-      const int ex = e % PX, ey = (e / PX) % PY, ez = e / (PX * PY);
-      const int gx = wrap_near(ox + ex - PHI_HALO, geo.nx), gy = wrap_near(oy + ey - PHI_HALO, geo.ny);
-      const int gz = DIM == 3 ? wrap_near(oz + ez - PHI_HALO, geo.nz) : 0;
-      phs[e] = phi[gx + geo.nx * (gy + geo.ny * gz)];
-    }
-    __syncthreads();
-    // (2) indicator everywhere on tile + 3, normal where the indicator passes the gate
-    for (int e = threadIdx.x; e < NNQ; e += NT_NCI) {
-      const int ex = e % NX, ey = (e / NX) % NY, ez = e / (NX * NY);
-      const int c = (ex + 1) + PX * ((ey + 1) + PY * (DIM == 3 ? ez + 1 : 0));
-      const T ph = phs[c];
-      const T pc = ph < (T)0 ? (T)0 : (ph > (T)1 ? (T)1 : ph);
-      const T q = pc * ((T)1 - pc);
-      nqs[DIM][e] = q;
-      if (q >= q_th) {
-        T gr[3], lap;
-        grad_lap<DIM, T>([&](int i) { return phs[c + L::cx[i] + PX * (L::cy[i] + PY * L::cz[i])]; },
-                         gr, lap);
-        T mag = gr[0] * gr[0] + gr[1] * gr[1];
-        if (DIM == 3) mag += gr[2] * gr[2];
-        mag = m_sqrt(mag);
-        const T den = mag + eps_n;
-#pragma unroll
-        for (int a = 0; a < DIM; ++a) nqs[a][e] = gr[a] / den;
-      }
-    }
-    __syncthreads();
-    // (3) list the gated cells of the tile
-    for (int e = threadIdx.x; e < TC; e += NT_NCI) {
-      const int lx = e % TX, ly = (e / TX) % TY, lz = e / (TX * TY);
-      const bool inside = ox + lx < geo.nx && oy + ly < geo.ny && oz + lz < geo.nz;
-      const int cc = (lx + NQ_HALO) + NX * ((ly + NQ_HALO) + NY * (DIM == 3 ? lz + NQ_HALO : 0));
-      short slot = -1;
-      if (inside && nqs[DIM][cc] >= q_th) {
-        slot = (short)atomicAdd(&s_ng, 1);
-        glist[slot] = (short)e;
-      }
-      gslot[e] = slot;
-    }
-    __syncthreads();
-    const int ng = s_ng;
-    // (4) partner search, one 8-lane group per gated cell, one plane per lane
-    for (int base = 0; base < ng; base += NGRP) {
-      const int gi = base + grp;
-      const bool cell_ok = gi < ng;
-      const int e = cell_ok ? glist[gi] : 0;
-      const int lx = e % TX, ly = (e / TX) % TY, lz = e / (TX * TY);
-      const int cc = (lx + NQ_HALO) + NX * ((ly + NQ_HALO) + NY * (DIM == 3 ? lz + NQ_HALO : 0));
-      const T qx = nqs[DIM][cc];
-      T nxv[3] = {0, 0, 0};
-#pragma unroll
-      for (int a = 0; a < DIM; ++a) nxv[a] = nqs[a][cc];
-      const T tol = eta * (qx > eps_q ? qx : eps_q);
-      const int plane = lane8 - w;                  // dz (3D) or dy (2D)
-      const bool lane_ok = cell_ok && lane8 <= 2 * w;
-      // pass 0
-      int bd2 = 1 << 30;
-      T bdot = (T)0;
-      if (lane_ok) {
-        const int dz0 = DIM == 3 ? plane : 0, ylo = DIM == 3 ? -w : plane, yhi = DIM == 3 ? w : plane;
-        for (int dy = ylo; dy <= yhi; ++dy)
-          for (int dx = -w; dx <= w; ++dx) {
-            if ((dx | dy | dz0) == 0) continue;
-            const int cy_ = cc + dx + NX * (dy + NY * dz0);
-            const T qy = nqs[DIM][cy_];
-            if (!(qy >= q_th)) continue;
-            if (!(m_abs(qy - qx) <= tol)) continue;
-            T dot = nxv[0] * nqs[0][cy_];
-            dot += nxv[1] * nqs[1][cy_];
-            if (DIM == 3) dot += nxv[2] * nqs[2][cy_];
-            if (!(dot <= cos_opp)) continue;
-            const int d2 = dx * dx + dy * dy + dz0 * dz0;
-            if (d2 < bd2 || (d2 == bd2 && dot < bdot)) {
-              bd2 = d2;
-              bdot = dot;
-            }
-          }
-      }
-      group_min(bd2, bdot);
-      const bool found = bd2 < (1 << 30);
-      // pass 1: first candidate in scan order at distance bd2 within tie_eps of bdot
-      int key = 1 << 30;
-      if (lane_ok && found) {
-        const int dz0 = DIM == 3 ? plane : 0, ylo = DIM == 3 ? -w : plane, yhi = DIM == 3 ? w : plane;
-        bool done = false;
-        for (int dy = ylo; dy <= yhi && !done; ++dy)
-          for (int dx = -w; dx <= w; ++dx) {
-            const int d2 = dx * dx + dy * dy + dz0 * dz0;
-            if (d2 != bd2) continue;
-            const int cy_ = cc + dx + NX * (dy + NY * dz0);
-            const T qy = nqs[DIM][cy_];
-            if (!(qy >= q_th)) continue;
-            if (!(m_abs(qy - qx) <= tol)) continue;
-            T dot = nxv[0] * nqs[0][cy_];
-            dot += nxv[1] * nqs[1][cy_];
-            if (DIM == 3) dot += nxv[2] * nqs[2][cy_];
-            if (!(dot <= cos_opp)) continue;
-            if (dot <= bdot + tie) {
-              // scan-order key: plane index, then row, then column
-              key = ((lane8 * 16) + (dy + 8)) * 16 + (dx + 8);
-              done = true;
-              break;
-            }
-          }
-      }
-#pragma unroll
-      for (int o = 1; o < 8; o <<= 1) {
-        const int ko = __shfl_xor(key, o, 64);
-        key = ko < key ? ko : key;
-      }
-      // (5) the group leader builds the repulsive flux of its cell
-      if (cell_ok && lane8 == 0) {
-        T Jv[3] = {0, 0, 0};
-        int packed = 0;
-        if (found && key < (1 << 30)) {
-          const int kdx = (key & 15) - 8, kdy = ((key >> 4) & 15) - 8, kpl = (key >> 8) - w;
-          const int bdx = kdx, bdy = DIM == 3 ? kdy : kpl, bdz = DIM == 3 ? kpl : 0;
-          const int cy_ = cc + bdx + NX * (bdy + NY * bdz);
-          const T qy = nqs[DIM][cy_];
-          T dot = nxv[0] * nqs[0][cy_];
-          dot += nxv[1] * nqs[1][cy_];
-          if (DIM == 3) dot += nxv[2] * nqs[2][cy_];
-          T qcl = (T)0.5 * (qx + qy);
-          if (qcl < eps_q) qcl = eps_q;
-          if (qcl > (T)0.25 - eps_q) qcl = (T)0.25 - eps_q;
-          const T ff = -dot > (T)0 ? -dot : (T)0;
-          packed = 1 + ((bdx + 8) | ((bdy + 8) << 5) | ((bdz + 8) << 10));
-          if (ff != (T)0) {
-            const T rn = m_sqrt((T)(bdx * bdx + bdy * bdy + bdz * bdz));
-            const T rh[3] = {(T)bdx / rn, (T)bdy / rn, (T)bdz / rn};
-            T nt[3] = {0, 0, 0}, nn = 0;
-#pragma unroll
-            for (int a = 0; a < DIM; ++a) {
-              nt[a] = nxv[a] - nqs[a][cy_];
-              nn += nt[a] * nt[a];
-            }
-            nn = m_sqrt(nn);
-            T ns[3] = {0, 0, 0};
-            if (nn < (T)1e-6) {
-#pragma unroll
-              for (int a = 0; a < DIM; ++a) ns[a] = rh[a];
-            } else {
-#pragma unroll
-              for (int a = 0; a < DIM; ++a) ns[a] = nt[a] / (nn + eps_n);
-            }
-            T ref = 0;
-            if (np.orient == 0) {
-#pragma unroll
-              for (int a = 0; a < DIM; ++a) ref += nxv[a] * ns[a];
-            } else {
-#pragma unroll
-              for (int a = 0; a < DIM; ++a) ref += rh[a] * ns[a];
-              ref *= (T)np.orient;
-            }
-            if (ref < (T)0) {
-#pragma unroll
-              for (int a = 0; a < DIM; ++a) ns[a] = -ns[a];
-            }
-            const T h = (T)np.width * m_acosh((T)1 / ((T)2 * m_sqrt(qcl)));
-            const T wh = (T)1 / ((T)1 + m_pow(h / (T)np.h0, (T)np.p_exp));
-            const T amp = (T)np.a_rep * qcl * wh * ff;
-#pragma unroll
-            for (int a = 0; a < DIM; ++a) Jv[a] = amp * ns[a];
-          }
-          my_active += 1u;
-        }
-#pragma unroll
-        for (int a = 0; a < DIM; ++a) gJ[gi][a] = Jv[a];
-        gpart[gi] = packed;
-      }
-    }
-    __syncthreads();
-    // (6) the tile's flux (zero where there is no partner)
-    for (int e = threadIdx.x; e < TC; e += NT_NCI) {
-      const int lx = e % TX, ly = (e / TX) % TY, lz = e / (TX * TY);
-      const int gx = ox + lx, gy = oy + ly, gz = oz + lz;
-      if (gx >= geo.nx || gy >= geo.ny || gz >= geo.nz) continue;
-      const int idx = gx + geo.nx * (gy + geo.ny * gz);
-      const int sl = gslot[e];
-#pragma unroll
-      for (int a = 0; a < DIM; ++a) J[a * geo.S + idx] = sl >= 0 ? gJ[sl][a] : (T)0;
-      if constexpr (DEBUG) {
-        const long long N = (long long)geo.nx * geo.ny * geo.nz;
-        const int pk = sl >= 0 ? gpart[sl] : 0;
-        chi_out[idx] = pk != 0;
-        part_out[idx] = pk ? ((pk - 1) & 31) - 8 : 0;
-        part_out[N + idx] = pk ? (((pk - 1) >> 5) & 31) - 8 : 0;
-        part_out[2 * N + idx] = pk ? (((pk - 1) >> 10) & 31) - 8 : 0;
-      }
-    }
-    __syncthreads();
+  const int tx = (int)(t % (unsigned)geo.ntx);
+  const int ty = (int)((t / (unsigned)geo.ntx) % (unsigned)geo.nty);
+  const int tz = (int)(t / ((unsigned)geo.ntx * (unsigned)geo.nty));
+  const int ox = tx * TX, oy = ty * TY, oz = tz * TZ;
+  if (threadIdx.x == 0) sm.ng = 0;
+  // (1) phi tile with halo
+  for (int e = threadIdx.x; e < NPH; e += NT_NCI) {
+    const int ex = e % PX, ey = (e / PX) % PY, ez = e / (PX * PY);
+    const int gx = wrap_near(ox + ex - PHI_HALO, geo.nx), gy = wrap_near(oy + ey - PHI_HALO, geo.ny);
+    const int gz = DIM == 3 ? wrap_near(oz + ez - PHI_HALO, geo.nz) : 0;
+    sm.phs[e] = phi[gx + geo.nx * (gy + geo.ny * gz)];
   }
+  __syncthreads();
+  // (2) indicator everywhere on tile + 3, normal where the indicator passes the gate
+  for (int e = threadIdx.x; e < NNQ; e += NT_NCI) {
+    const int ex = e % NX, ey = (e / NX) % NY, ez = e / (NX * NY);
+    const int c = (ex + 1) + PX * ((ey + 1) + PY * (DIM == 3 ? ez + 1 : 0));
+    const T ph = sm.phs[c];
+    const T pc = ph < (T)0 ? (T)0 : (ph > (T)1 ? (T)1 : ph);
+    const T q = pc * ((T)1 - pc);
+    sm.nqs[DIM][e] = q;
+    if (q >= q_th) {
+      T gr[3], lap;
+      grad_lap<DIM, T>([&](int i) { return sm.phs[c + L::cx[i] + PX * (L::cy[i] + PY * L::cz[i])]; },
+                       gr, lap);
+      T mag = gr[0] * gr[0] + gr[1] * gr[1];
+      if (DIM == 3) mag += gr[2] * gr[2];
+      mag = m_sqrt(mag);
+      const T den = mag + eps_n;
+#pragma unroll
+      for (int a = 0; a < DIM; ++a) sm.nqs[a][e] = gr[a] / den;
+    }
+  }
+  __syncthreads();
+  // (3) list the gated cells of the tile
+  for (int e = threadIdx.x; e < TC; e += NT_NCI) {
+    const int lx = e % TX, ly = (e / TX) % TY, lz = e / (TX * TY);
+    const bool inside = ox + lx < geo.nx && oy + ly < geo.ny && oz + lz < geo.nz;
+    const int cc = (lx + NQ_HALO) + NX * ((ly + NQ_HALO) + NY * (DIM == 3 ? lz + NQ_HALO : 0));
+    short slot = -1;
+    if (inside && sm.nqs[DIM][cc] >= q_th) {
+      slot = (short)atomicAdd(&sm.ng, 1);
+      sm.glist[slot] = (short)e;
+    }
+    sm.gslot[e] = slot;
+  }
+  __syncthreads();
+  const int ng = sm.ng;
+  // (4) partner search, one 8-lane group per gated cell, one plane per lane
+  for (int base = 0; base < ng; base += NGRP) {
+    const int gi = base + grp;
+    const bool cell_ok = gi < ng;
+    const int e = cell_ok ? sm.glist[gi] : 0;
+    const int lx = e % TX, ly = (e / TX) % TY, lz = e / (TX * TY);
+    const int cc = (lx + NQ_HALO) + NX * ((ly + NQ_HALO) + NY * (DIM == 3 ? lz + NQ_HALO : 0));
+    const T qx = sm.nqs[DIM][cc];
+    T nxv[3] = {0, 0, 0};
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) nxv[a] = sm.nqs[a][cc];
+    const T tol = eta * (qx > eps_q ? qx : eps_q);
+    const int plane = lane8 - w;                  // dz (3D) or dy (2D)
+    const bool lane_ok = cell_ok && lane8 <= 2 * w;
+    // pass 0
+    int bd2 = 1 << 30;
+    T bdot = (T)0;
+    if (lane_ok) {
+      const int dz0 = DIM == 3 ? plane : 0, ylo = DIM == 3 ? -w : plane, yhi = DIM == 3 ? w : plane;
+      for (int dy = ylo; dy <= yhi; ++dy)
+        for (int dx = -w; dx <= w; ++dx) {
+          if ((dx | dy | dz0) == 0) continue;
+          const int cy_ = cc + dx + NX * (dy + NY * dz0);
+          const T qy = sm.nqs[DIM][cy_];
+          if (!(qy >= q_th)) continue;
+          if (!(m_abs(qy - qx) <= tol)) continue;
+          T dot = nxv[0] * sm.nqs[0][cy_];
+          dot += nxv[1] * sm.nqs[1][cy_];
+          if (DIM == 3) dot += nxv[2] * sm.nqs[2][cy_];
+          if (!(dot <= cos_opp)) continue;
+          const int d2 = dx * dx + dy * dy + dz0 * dz0;
+          if (d2 < bd2 || (d2 == bd2 && dot < bdot)) {
+            bd2 = d2;
+            bdot = dot;
+          }
+        }
+    }
+    group_min(bd2, bdot);
+    const bool found = bd2 < (1 << 30);
+    // pass 1: first candidate in scan order at distance bd2 within tie_eps of bdot
+    int key = 1 << 30;
+    if (lane_ok && found) {
+      const int dz0 = DIM == 3 ? plane : 0, ylo = DIM == 3 ? -w : plane, yhi = DIM == 3 ? w : plane;
+      bool done = false;
+      for (int dy = ylo; dy <= yhi && !done; ++dy)
+        for (int dx = -w; dx <= w; ++dx) {
+          const int d2 = dx * dx + dy * dy + dz0 * dz0;
+          if (d2 != bd2) continue;
+          const int cy_ = cc + dx + NX * (dy + NY * dz0);
+          const T qy = sm.nqs[DIM][cy_];
+          if (!(qy >= q_th)) continue;
+          if (!(m_abs(qy - qx) <= tol)) continue;
+          T dot = nxv[0] * sm.nqs[0][cy_];
+          dot += nxv[1] * sm.nqs[1][cy_];
+          if (DIM == 3) dot += nxv[2] * sm.nqs[2][cy_];
+          if (!(dot <= cos_opp)) continue;
+          if (dot <= bdot + tie) {
+            // scan-order key: plane index, then row, then column
+            key = ((lane8 * 16) + (dy + 8)) * 16 + (dx + 8);
+            done = true;
+            break;
+          }
+        }
+    }
+#pragma unroll
+    for (int o = 1; o < 8; o <<= 1) {
+      const int ko = __shfl_xor(key, o, 64);
+      key = ko < key ? ko : key;
+    }
+    // (5) the group leader builds the repulsive flux of its cell
+    if (cell_ok && lane8 == 0) {
+      T Jv[3] = {0, 0, 0};
+      int packed = 0;
+      if (found && key < (1 << 30)) {
+        const int kdx = (key & 15) - 8, kdy = ((key >> 4) & 15) - 8, kpl = (key >> 8) - w;
+        const int bdx = kdx, bdy = DIM == 3 ? kdy : kpl, bdz = DIM == 3 ? kpl : 0;
+        const int cy_ = cc + bdx + NX * (bdy + NY * bdz);
+        const T qy = sm.nqs[DIM][cy_];
+        T dot = nxv[0] * sm.nqs[0][cy_];
+        dot += nxv[1] * sm.nqs[1][cy_];
+        if (DIM == 3) dot += nxv[2] * sm.nqs[2][cy_];
+        T qcl = (T)0.5 * (qx + qy);
+        if (qcl < eps_q) qcl = eps_q;
+        if (qcl > (T)0.25 - eps_q) qcl = (T)0.25 - eps_q;
+        const T ff = -dot > (T)0 ? -dot : (T)0;
+        packed = 1 + ((bdx + 8) | ((bdy + 8) << 5) | ((bdz + 8) << 10));
+        if (ff != (T)0) {
+          const T rn = m_sqrt((T)(bdx * bdx + bdy * bdy + bdz * bdz));
+          const T rh[3] = {(T)bdx / rn, (T)bdy / rn, (T)bdz / rn};
+          T nt[3] = {0, 0, 0}, nn = 0;
+#pragma unroll
+          for (int a = 0; a < DIM; ++a) {
+            nt[a] = nxv[a] - sm.nqs[a][cy_];
+            nn += nt[a] * nt[a];
+          }
+          nn = m_sqrt(nn);
+          T ns[3] = {0, 0, 0};
+          if (nn < (T)1e-6) {
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) ns[a] = rh[a];
+          } else {
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) ns[a] = nt[a] / (nn + eps_n);
+          }
+          T ref = 0;
+          if (np.orient == 0) {
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) ref += nxv[a] * ns[a];
+          } else {
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) ref += rh[a] * ns[a];
+            ref *= (T)np.orient;
+          }
+          if (ref < (T)0) {
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) ns[a] = -ns[a];
+          }
+          const T h = (T)np.width * m_acosh((T)1 / ((T)2 * m_sqrt(qcl)));
+          const T wh = (T)1 / ((T)1 + m_pow(h / (T)np.h0, (T)np.p_exp));
+          const T amp = (T)np.a_rep * qcl * wh * ff;
+#pragma unroll
+          for (int a = 0; a < DIM; ++a) Jv[a] = amp * ns[a];
+        }
+        my_active += 1u;
+      }
+#pragma unroll
+      for (int a = 0; a < DIM; ++a) sm.gJ[gi][a] = Jv[a];
+      sm.gpart[gi] = packed;
+    }
+  }
+  __syncthreads();
+  // (6) the tile's flux (zero where there is no partner)
+  for (int e = threadIdx.x; e < TC; e += NT_NCI) {
+    const int lx = e % TX, ly = (e / TX) % TY, lz = e / (TX * TY);
+    const int gx = ox + lx, gy = oy + ly, gz = oz + lz;
+    if (gx >= geo.nx || gy >= geo.ny || gz >= geo.nz) continue;
+    const int idx = gx + geo.nx * (gy + geo.ny * gz);
+    const int sl = sm.gslot[e];
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) J[a * geo.S + idx] = sl >= 0 ? sm.gJ[sl][a] : (T)0;
+    if constexpr (DEBUG) {
+      const long long N = (long long)geo.nx * geo.ny * geo.nz;
+      const int pk = sl >= 0 ? sm.gpart[sl] : 0;
+      chi_out[idx] = pk != 0;
+      part_out[idx] = pk ? ((pk - 1) & 31) - 8 : 0;
+      part_out[N + idx] = pk ? (((pk - 1) >> 5) & 31) - 8 : 0;
+      part_out[2 * N + idx] = pk ? (((pk - 1) >> 10) & 31) - 8 : 0;
+    }
+  }
+  __syncthreads();
+}
+
+template <int DIM, typename T, bool DEBUG>
+__global__ __launch_bounds__(NT_NCI) void k_nci(const T* __restrict__ phi, T* __restrict__ J,
+                                                int* __restrict__ chi_out, int* __restrict__ part_out,
+                                                const unsigned* __restrict__ list,
+                                                const unsigned* __restrict__ cnt,
+                                                unsigned* __restrict__ flags_other,
+                                                const unsigned* __restrict__ list_other,
+                                                const unsigned* __restrict__ cnt_other,
+                                                unsigned* __restrict__ nci_count, Geo geo, NciP np) {
+  __shared__ NciShared<DIM, T> sm;
+  nci_clear_other(flags_other, list_other, cnt_other);
+  const unsigned ntiles = *cnt;
+  unsigned my_active = 0;
+  for (unsigned k = blockIdx.x; k < ntiles; k += gridDim.x)
+    nci_tile<DIM, T, DEBUG>(sm, list[k], phi, J, chi_out, part_out, geo, np, my_active);
   my_active = wave_sum(my_active);
   if ((threadIdx.x & 63) == 0 && my_active) atomicAdd(nci_count, my_active);
 }
@@ -554,254 +637,316 @@ __device__ __forceinline__ double m_rcp(double a) { return 1.0 / a; }
 //   H2:B2/(2cs^4) = 4.5 c.B2.c - 1.5 tr B2,
 //   H3...B3/(6cs^6) = 4.5 cu (cu^2 - u^2) + (1-omega)(13.5 cu c.A2.c - 4.5 cu trA2 - 9 c.A2.u).
 // Each opposite pair (c, -c) shares the even part and flips the odd part.
+// One cell of the fused collide + stream (AA parity PAR).  MODE_STEP updates
+// the populations in place; MODE_STEP_DIAG also fills acc with the cell's
+// contributions to the FP64 diagnostics; MODE_DRY leaves the populations and
+// writes p*, rho, u, F to macro (when given).
 template <int DIM, int PAR, int MODE, typename T, typename FS, typename GS, bool OFF32>
-__global__ __launch_bounds__(NT) void k_collide(Planes<FS, GS> pl,
-                                                const T* __restrict__ phi,
-                                                const T* __restrict__ J,
-                                                const unsigned* __restrict__ flags,
-                                                unsigned* __restrict__ cnt_other, Geo geo,
-                                                PhysT<T> pp, int nci_on,
-                                                T* __restrict__ macro,
-                                                double* __restrict__ partials) {
+__device__ __forceinline__ void collide_cell(const Planes<FS, GS>& pl, const T* __restrict__ phi,
+                                             const T* __restrict__ J,
+                                             const unsigned* __restrict__ flags, const Geo& geo,
+                                             const PhysT<T>& pp, int nci_on, T* __restrict__ macro,
+                                             int x, int y, int z, double acc[NPART]) {
   using H = Hydro<DIM>;
   using P = Phase<DIM>;
   using TL = NciTile<DIM, T>;
   constexpr int Q = H::Q, QG = P::Q;
+  const Nbr nb(x, y, z, geo);
+  const unsigned idx = (unsigned)nb(0, 0, 0);
+  const long long S = geo.S;
+  // ---- phase field around the cell: grad, lap, mu_phi
+  T gr[3], lap;
+  grad_lap<DIM, T>([&](int i) { return *plane_at<OFF32>(phi, (unsigned)nb(H::cx[i], H::cy[i], H::cz[i])); },
+                   gr, lap);
+  const T ph = *plane_at<OFF32>(phi, idx);
+  T gmag = gr[0] * gr[0] + gr[1] * gr[1];
+  if (DIM == 3) gmag += gr[2] * gr[2];
+  gmag = m_sqrt(gmag);
+  const T inv_g = m_rcp(gmag + pp.eps_n);
+  const T mu = pp.beta4 * ph * (ph - (T)1) * (ph - (T)0.5) - pp.kappa * lap;
+  // ---- mixture (linear rho, linear dynamic viscosity)
+  const T rho = pp.rho_g + pp.drho * ph;
+  const T inv_rho = m_rcp(rho);
+  const T nu = (pp.mu_a + pp.mu_b * ph) * inv_rho;
+  const T omega = m_rcp((T)0.5 + (T)3 * nu);
+  // ---- hydrodynamic populations and their moments
+  T fi[Q];
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const FS* fp = pl.f[PAR == 0 ? i : opp(i)];
+    const unsigned src = PAR == 0 ? idx : (unsigned)nb(-H::cx[i], -H::cy[i], -H::cz[i]);
+    fi[i] = Store<FS>::ld(plane_at<OFF32>(fp, src), pp.fref[i]);
+  }
+  T ps = fi[0], m[3] = {0, 0, 0}, M2[6] = {0, 0, 0, 0, 0, 0};  // xx yy zz xy xz yz
+#pragma unroll
+  for (int i = 1; i < Q; i += 2) {
+    const T s = fi[i] + fi[i + 1], d = fi[i] - fi[i + 1];
+    ps += s;
+    const int cx = H::cx[i], cy = H::cy[i], cz = H::cz[i];
+    if (cx) m[0] += cx > 0 ? d : -d;
+    if (cy) m[1] += cy > 0 ? d : -d;
+    if (cz) m[2] += cz > 0 ? d : -d;
+    if (cx) M2[0] += s;
+    if (cy) M2[1] += s;
+    if (cz) M2[2] += s;
+    if (cx && cy) M2[3] += cx * cy > 0 ? s : -s;
+    if (cx && cz) M2[4] += cx * cz > 0 ? s : -s;
+    if (cy && cz) M2[5] += cy * cz > 0 ? s : -s;
+  }
+  // ---- forces (Eq. Fsplit): capillary, pressure correction, repulsion, buoyancy
+  T Jv[3] = {0, 0, 0};
+  if (nci_on) {
+    const unsigned tile = (unsigned)(x / TL::TX + geo.ntx * (y / TL::TY + geo.nty * (z / TL::TZ)));
+    if (flags[tile]) {
+#pragma unroll
+      for (int a = 0; a < DIM; ++a) Jv[a] = *plane_at<OFF32>(J + a * S, idx);
+    }
+  }
+  const T cs2 = (T)(1.0 / 3.0);
+  const T inv2rho = (T)0.5 * inv_rho;
+  const T pc = ps * cs2;
+  const T prho = pc * pp.drho;
+  const T dens = rho - pp.rho_mean;
+  T Fp[3], up[3], F[3], u[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    Fp[a] = a < DIM ? (mu - prho) * gr[a] + rho * Jv[a] + dens * pp.g[a] : (T)0;
+    up[a] = m[a] + Fp[a] * inv2rho;
+  }
+  // viscous correction (Eq. Fnu) from the second moment of f - feq(p*, u')
+  {
+    const T Pxx = M2[0] - pc - up[0] * up[0], Pyy = M2[1] - pc - up[1] * up[1];
+    const T Pzz = M2[2] - pc - up[2] * up[2];
+    const T Pxy = M2[3] - up[0] * up[1], Pxz = M2[4] - up[0] * up[2], Pyz = M2[5] - up[1] * up[2];
+    const T kf = -(T)3 * nu * omega * pp.drho;
+    F[0] = Fp[0] + kf * (Pxx * gr[0] + Pxy * gr[1] + Pxz * gr[2]);
+    F[1] = Fp[1] + kf * (Pxy * gr[0] + Pyy * gr[1] + Pyz * gr[2]);
+    F[2] = DIM == 3 ? Fp[2] + kf * (Pxz * gr[0] + Pyz * gr[1] + Pzz * gr[2]) : (T)0;
+  }
+#pragma unroll
+  for (int a = 0; a < 3; ++a) u[a] = m[a] + F[a] * inv2rho;
+  if constexpr (MODE != MODE_DRY) {
+    const T uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    const T om1 = (T)1 - omega;
+    // second-order Hermite coefficient of f - feq + S/2, and the post-collision ones
+    T A[6], B[6];
+    {
+      const T gxx = u[0] * F[0] * inv2rho, gyy = u[1] * F[1] * inv2rho, gzz = u[2] * F[2] * inv2rho;
+      const T gxy = (u[0] * F[1] + u[1] * F[0]) * inv2rho;
+      const T gxz = (u[0] * F[2] + u[2] * F[0]) * inv2rho;
+      const T gyz = (u[1] * F[2] + u[2] * F[1]) * inv2rho;
+      const T uxx = u[0] * u[0], uyy = u[1] * u[1], uzz = u[2] * u[2];
+      const T uxy = u[0] * u[1], uxz = u[0] * u[2], uyz = u[1] * u[2];
+      A[0] = M2[0] - pc - uxx + (T)2 * gxx;
+      A[1] = M2[1] - pc - uyy + (T)2 * gyy;
+      A[2] = DIM == 3 ? M2[2] - pc - uzz + (T)2 * gzz : (T)0;
+      A[3] = M2[3] - uxy + gxy;
+      A[4] = DIM == 3 ? M2[4] - uxz + gxz : (T)0;
+      A[5] = DIM == 3 ? M2[5] - uyz + gyz : (T)0;
+      B[0] = uxx + om1 * A[0] + (T)2 * gxx;
+      B[1] = uyy + om1 * A[1] + (T)2 * gyy;
+      B[2] = DIM == 3 ? uzz + om1 * A[2] + (T)2 * gzz : (T)0;
+      B[3] = uxy + om1 * A[3] + gxy;
+      B[4] = DIM == 3 ? uxz + om1 * A[4] + gxz : (T)0;
+      B[5] = DIM == 3 ? uyz + om1 * A[5] + gyz : (T)0;
+    }
+    const T trA = A[0] + A[1] + A[2];
+    const T trB = B[0] + B[1] + B[2];
+    const T Au[3] = {A[0] * u[0] + A[3] * u[1] + A[4] * u[2], A[3] * u[0] + A[1] * u[1] + A[5] * u[2],
+                     A[4] * u[0] + A[5] * u[1] + A[2] * u[2]};
+    const T A1[3] = {u[0] + F[0] * inv2rho, u[1] + F[1] * inv2rho, u[2] + F[2] * inv2rho};
+    const T base = ps - (T)1.5 * trB;
+    const T k3 = (T)13.5 * om1, k3t = (T)4.5 * om1 * trA, k3u = (T)9 * om1;
+    Store<FS>::st(plane_at<OFF32>(pl.f[0], idx), wt<H, T>(0) * base, pp.fref[0]);
+#pragma unroll
+    for (int i = 1; i < Q; i += 2) {
+      const int cx = H::cx[i], cy = H::cy[i], cz = H::cz[i];
+      const T w = wt<H, T>(i);
+      const T cu = sdot(cx, cy, cz, u[0], u[1], u[2]);
+      const T cA1 = sdot(cx, cy, cz, A1[0], A1[1], A1[2]);
+      const T cAu = sdot(cx, cy, cz, Au[0], Au[1], Au[2]);
+      const T cAc = ccdot(cx, cy, cz, A);
+      const T cBc = ccdot(cx, cy, cz, B);
+      const T ev = w * fmad((T)4.5, cBc, base);
+      const T t3 = fmad(cu, fmad(k3, cAc, fmad((T)4.5, fmad(cu, cu, -uu), -k3t)), -(k3u * cAu));
+      const T od = w * fmad((T)3, cA1, t3);
+      const T fa = ev + od, fb = ev - od;   // directions i and opp(i)
+      FS* const pi = pl.f[i];
+      FS* const pj = pl.f[i + 1];
+      if constexpr (PAR == 0) {
+        Store<FS>::st(plane_at<OFF32>(pj, idx), fa, pp.fref[i]);
+        Store<FS>::st(plane_at<OFF32>(pi, idx), fb, pp.fref[i]);
+      } else {
+        Store<FS>::st(plane_at<OFF32>(pi, (unsigned)nb(cx, cy, cz)), fa, pp.fref[i]);
+        Store<FS>::st(plane_at<OFF32>(pj, (unsigned)nb(-cx, -cy, -cz)), fb, pp.fref[i]);
+      }
+    }
+    // ---- conservative Allen-Cahn populations: BGK towards
+    //      geq_k = w_k (phi + c_k . j / cs_phi^2), j = phi u + M (4/W) phi (1-phi) n
+    const T kc = pp.kc * ph * ((T)1 - ph) * inv_g;
+    const T jv[3] = {ph * u[0] + kc * gr[0], ph * u[1] + kc * gr[1], ph * u[2] + kc * gr[2]};
+    const T itp = pp.inv_tau_phi;
+    T gi[QG];
+#pragma unroll
+    for (int k = 0; k < QG; ++k) {
+      const GS* gp = pl.g[PAR == 0 ? k : opp(k)];
+      const unsigned src = PAR == 0 ? idx : (unsigned)nb(-P::cx[k], -P::cy[k], -P::cz[k]);
+      gi[k] = (T)*plane_at<OFF32>(gp, src);
+    }
+    // geq - g is formed with the product unrounded: a rounded w_k (phi + c.j/cs^2)
+    // (the D2Q9 weights are not powers of two) would bias the phase-field mass
+    // of every step, like weights that do not sum to one.
+    *plane_at<OFF32>(pl.g[0], idx) = (GS)fmad(fmad(wt<P, T>(0), ph, -gi[0]), itp, gi[0]);
+#pragma unroll
+    for (int k = 1; k < QG; k += 2) {
+      const int cx = P::cx[k], cy = P::cy[k], cz = P::cz[k];
+      const T cj = sdot(cx, cy, cz, jv[0], jv[1], jv[2]) * (T)P::inv_cs2;
+      const T wk = wt<P, T>(k);
+      const T ga = fmad(fmad(wk, ph + cj, -gi[k]), itp, gi[k]);
+      const T gb = fmad(fmad(wk, ph - cj, -gi[k + 1]), itp, gi[k + 1]);
+      GS* const pk = pl.g[k];
+      GS* const pk1 = pl.g[k + 1];
+      if constexpr (PAR == 0) {
+        *plane_at<OFF32>(pk1, idx) = (GS)ga;
+        *plane_at<OFF32>(pk, idx) = (GS)gb;
+      } else {
+        *plane_at<OFF32>(pk, (unsigned)nb(cx, cy, cz)) = (GS)ga;
+        *plane_at<OFF32>(pk1, (unsigned)nb(-cx, -cy, -cz)) = (GS)gb;
+      }
+    }
+  } else if (macro) {
+    // dry evaluation: macroscopic fields of the current state
+    macro[idx] = ps;
+    macro[S + idx] = rho;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+      macro[(2 + a) * S + idx] = u[a];
+      macro[(2 + DIM + a) * S + idx] = F[a];
+    }
+  }
+  if constexpr (MODE != MODE_STEP) {
+    const double dr = (double)rho;
+    acc[0] = (double)ps;
+    acc[1] = dr * (double)u[0];
+    acc[2] = dr * (double)u[1];
+    acc[3] = dr * (double)u[2];
+    const double sp2 = (double)u[0] * (double)u[0] + (double)u[1] * (double)u[1] + (double)u[2] * (double)u[2];
+    acc[4] = 0.5 * dr * sp2;
+    acc[5] = sqrt(sp2);
+    const bool fin = isfinite((double)ps) && isfinite(sp2);
+    acc[6] = fin ? 0.0 : 1.0;
+    if (!fin) acc[5] = 0.0;
+  }
+}
+
+template <int DIM, int PAR, int MODE, typename T, typename FS, typename GS, bool OFF32>
+__global__ __launch_bounds__(NT) void k_collide(Planes<FS, GS> pl, const T* __restrict__ phi,
+                                                const T* __restrict__ J,
+                                                const unsigned* __restrict__ flags,
+                                                unsigned* __restrict__ cnt_other, Geo geo,
+                                                PhysT<T> pp, int nci_on, T* __restrict__ macro,
+                                                double* __restrict__ partials) {
   if (nci_on && blockIdx.x == 0 && threadIdx.x == 0) *cnt_other = 0u;
-  const int t = swizzled_block();
-  const int bx = t % geo.nbx, r = t / geo.nbx, by = r % geo.nby, z = r / geo.nby;
-  const int x = bx * BX + (int)(threadIdx.x & (BX - 1)), y = by * BY + (int)(threadIdx.x / BX);
+  int x, y, z;
+  block_cell(swizzled_block(), geo, x, y, z);
   const bool valid = x < geo.nx && y < geo.ny;
   double acc[NPART] = {0, 0, 0, 0, 0, 0, 0, 0};
   if (MODE == MODE_STEP && !valid) return;
-  if (valid) {
-    const Nbr nb(x, y, z, geo);
-    const unsigned idx = (unsigned)nb(0, 0, 0);
-    const long long S = geo.S;
-    // ---- phase field around the cell: grad, lap, mu_phi
-    T gr[3], lap;
-    grad_lap<DIM, T>([&](int i) { return *plane_at<OFF32>(phi, (unsigned)nb(H::cx[i], H::cy[i], H::cz[i])); },
-                     gr, lap);
-    const T ph = *plane_at<OFF32>(phi, idx);
-    T gmag = gr[0] * gr[0] + gr[1] * gr[1];
-    if (DIM == 3) gmag += gr[2] * gr[2];
-    gmag = m_sqrt(gmag);
-    const T inv_g = m_rcp(gmag + pp.eps_n);
-    const T mu = pp.beta4 * ph * (ph - (T)1) * (ph - (T)0.5) - pp.kappa * lap;
-    // ---- mixture (linear rho, linear dynamic viscosity)
-    const T rho = pp.rho_g + pp.drho * ph;
-    const T inv_rho = m_rcp(rho);
-    const T nu = (pp.mu_a + pp.mu_b * ph) * inv_rho;
-    const T omega = m_rcp((T)0.5 + (T)3 * nu);
-    // ---- hydrodynamic populations and their moments
-    T fi[Q];
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-      const FS* fp = pl.f[PAR == 0 ? i : opp(i)];
-      const unsigned src = PAR == 0 ? idx : (unsigned)nb(-H::cx[i], -H::cy[i], -H::cz[i]);
-      fi[i] = Store<FS>::ld(plane_at<OFF32>(fp, src), pp.fref[i]);
-    }
-    T ps = fi[0], m[3] = {0, 0, 0}, M2[6] = {0, 0, 0, 0, 0, 0};  // xx yy zz xy xz yz
-#pragma unroll
-    for (int i = 1; i < Q; i += 2) {
-      const T s = fi[i] + fi[i + 1], d = fi[i] - fi[i + 1];
-      ps += s;
-      const int cx = H::cx[i], cy = H::cy[i], cz = H::cz[i];
-      if (cx) m[0] += cx > 0 ? d : -d;
-      if (cy) m[1] += cy > 0 ? d : -d;
-      if (cz) m[2] += cz > 0 ? d : -d;
-      if (cx) M2[0] += s;
-      if (cy) M2[1] += s;
-      if (cz) M2[2] += s;
-      if (cx && cy) M2[3] += cx * cy > 0 ? s : -s;
-      if (cx && cz) M2[4] += cx * cz > 0 ? s : -s;
-      if (cy && cz) M2[5] += cy * cz > 0 ? s : -s;
-    }
-    // ---- forces (Eq. Fsplit): capillary, pressure correction, repulsion, buoyancy
-    T Jv[3] = {0, 0, 0};
-    if (nci_on) {
-      const unsigned tile = (unsigned)(x / TL::TX + geo.ntx * (y / TL::TY + geo.nty * (z / TL::TZ)));
-      if (flags[tile]) {
-#pragma unroll
-        for (int a = 0; a < DIM; ++a) Jv[a] = *plane_at<OFF32>(J + a * S, idx);
-      }
-    }
-    const T cs2 = (T)(1.0 / 3.0);
-    const T inv2rho = (T)0.5 * inv_rho;
-    const T pc = ps * cs2;
-    const T prho = pc * pp.drho;
-    const T dens = rho - pp.rho_mean;
-    T Fp[3], up[3], F[3], u[3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      Fp[a] = a < DIM ? (mu - prho) * gr[a] + rho * Jv[a] + dens * pp.g[a] : (T)0;
-      up[a] = m[a] + Fp[a] * inv2rho;
-    }
-    // viscous correction (Eq. Fnu) from the second moment of f - feq(p*, u')
-    {
-      const T Pxx = M2[0] - pc - up[0] * up[0], Pyy = M2[1] - pc - up[1] * up[1];
-      const T Pzz = M2[2] - pc - up[2] * up[2];
-      const T Pxy = M2[3] - up[0] * up[1], Pxz = M2[4] - up[0] * up[2], Pyz = M2[5] - up[1] * up[2];
-      const T kf = -(T)3 * nu * omega * pp.drho;
-      F[0] = Fp[0] + kf * (Pxx * gr[0] + Pxy * gr[1] + Pxz * gr[2]);
-      F[1] = Fp[1] + kf * (Pxy * gr[0] + Pyy * gr[1] + Pyz * gr[2]);
-      F[2] = DIM == 3 ? Fp[2] + kf * (Pxz * gr[0] + Pyz * gr[1] + Pzz * gr[2]) : (T)0;
-    }
-#pragma unroll
-    for (int a = 0; a < 3; ++a) u[a] = m[a] + F[a] * inv2rho;
-    if constexpr (MODE != MODE_DRY) {
-      const T uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
-      const T om1 = (T)1 - omega;
-      // second-order Hermite coefficient of f - feq + S/2, and the post-collision ones
-      T A[6], B[6];
-      {
-        const T gxx = u[0] * F[0] * inv2rho, gyy = u[1] * F[1] * inv2rho, gzz = u[2] * F[2] * inv2rho;
-        const T gxy = (u[0] * F[1] + u[1] * F[0]) * inv2rho;
-        const T gxz = (u[0] * F[2] + u[2] * F[0]) * inv2rho;
-        const T gyz = (u[1] * F[2] + u[2] * F[1]) * inv2rho;
-        const T uxx = u[0] * u[0], uyy = u[1] * u[1], uzz = u[2] * u[2];
-        const T uxy = u[0] * u[1], uxz = u[0] * u[2], uyz = u[1] * u[2];
-        A[0] = M2[0] - pc - uxx + (T)2 * gxx;
-        A[1] = M2[1] - pc - uyy + (T)2 * gyy;
-        A[2] = DIM == 3 ? M2[2] - pc - uzz + (T)2 * gzz : (T)0;
-        A[3] = M2[3] - uxy + gxy;
-        A[4] = DIM == 3 ? M2[4] - uxz + gxz : (T)0;
-        A[5] = DIM == 3 ? M2[5] - uyz + gyz : (T)0;
-        B[0] = uxx + om1 * A[0] + (T)2 * gxx;
-        B[1] = uyy + om1 * A[1] + (T)2 * gyy;
-        B[2] = DIM == 3 ? uzz + om1 * A[2] + (T)2 * gzz : (T)0;
-        B[3] = uxy + om1 * A[3] + gxy;
-        B[4] = DIM == 3 ? uxz + om1 * A[4] + gxz : (T)0;
-        B[5] = DIM == 3 ? uyz + om1 * A[5] + gyz : (T)0;
-      }
-      const T trA = A[0] + A[1] + A[2];
-      const T trB = B[0] + B[1] + B[2];
-      const T Au[3] = {A[0] * u[0] + A[3] * u[1] + A[4] * u[2], A[3] * u[0] + A[1] * u[1] + A[5] * u[2],
-                       A[4] * u[0] + A[5] * u[1] + A[2] * u[2]};
-      const T A1[3] = {u[0] + F[0] * inv2rho, u[1] + F[1] * inv2rho, u[2] + F[2] * inv2rho};
-      const T base = ps - (T)1.5 * trB;
-      const T k3 = (T)13.5 * om1, k3t = (T)4.5 * om1 * trA, k3u = (T)9 * om1;
-      Store<FS>::st(plane_at<OFF32>(pl.f[0], idx), wt<H, T>(0) * base, pp.fref[0]);
-#pragma unroll
-      for (int i = 1; i < Q; i += 2) {
-        const int cx = H::cx[i], cy = H::cy[i], cz = H::cz[i];
-        const T w = wt<H, T>(i);
-        const T cu = (T)cx * u[0] + (T)cy * u[1] + (T)cz * u[2];
-        const T cA1 = (T)cx * A1[0] + (T)cy * A1[1] + (T)cz * A1[2];
-        const T cAu = (T)cx * Au[0] + (T)cy * Au[1] + (T)cz * Au[2];
-        const T cAc = (T)(cx * cx) * A[0] + (T)(cy * cy) * A[1] + (T)(cz * cz) * A[2] +
-                      (T)2 * ((T)(cx * cy) * A[3] + (T)(cx * cz) * A[4] + (T)(cy * cz) * A[5]);
-        const T cBc = (T)(cx * cx) * B[0] + (T)(cy * cy) * B[1] + (T)(cz * cz) * B[2] +
-                      (T)2 * ((T)(cx * cy) * B[3] + (T)(cx * cz) * B[4] + (T)(cy * cz) * B[5]);
-        const T ev = w * (base + (T)4.5 * cBc);
-        const T t3 = cu * ((T)4.5 * (cu * cu - uu) + k3 * cAc - k3t) - k3u * cAu;
-        const T od = w * ((T)3 * cA1 + t3);
-        const T fa = ev + od, fb = ev - od;   // directions i and opp(i)
-        FS* const pi = pl.f[i];
-        FS* const pj = pl.f[i + 1];
-        if constexpr (PAR == 0) {
-          Store<FS>::st(plane_at<OFF32>(pj, idx), fa, pp.fref[i]);
-          Store<FS>::st(plane_at<OFF32>(pi, idx), fb, pp.fref[i]);
-        } else {
-          Store<FS>::st(plane_at<OFF32>(pi, (unsigned)nb(cx, cy, cz)), fa, pp.fref[i]);
-          Store<FS>::st(plane_at<OFF32>(pj, (unsigned)nb(-cx, -cy, -cz)), fb, pp.fref[i]);
-        }
-      }
-      // ---- conservative Allen-Cahn populations: BGK towards
-      //      geq_k = w_k (phi + c_k . j / cs_phi^2), j = phi u + M (4/W) phi (1-phi) n
-      const T kc = pp.kc * ph * ((T)1 - ph) * inv_g;
-      const T jv[3] = {ph * u[0] + kc * gr[0], ph * u[1] + kc * gr[1], ph * u[2] + kc * gr[2]};
-      const T itp = pp.inv_tau_phi;
-      T gi[QG];
-#pragma unroll
-      for (int k = 0; k < QG; ++k) {
-        const GS* gp = pl.g[PAR == 0 ? k : opp(k)];
-        const unsigned src = PAR == 0 ? idx : (unsigned)nb(-P::cx[k], -P::cy[k], -P::cz[k]);
-        gi[k] = (T)*plane_at<OFF32>(gp, src);
-      }
-      *plane_at<OFF32>(pl.g[0], idx) = (GS)(gi[0] - (gi[0] - wt<P, T>(0) * ph) * itp);
-#pragma unroll
-      for (int k = 1; k < QG; k += 2) {
-        const int cx = P::cx[k], cy = P::cy[k], cz = P::cz[k];
-        const T cj = ((T)cx * jv[0] + (T)cy * jv[1] + (T)cz * jv[2]) * (T)P::inv_cs2;
-        const T wk = wt<P, T>(k);
-        const T ga = gi[k] - (gi[k] - wk * (ph + cj)) * itp;
-        const T gb = gi[k + 1] - (gi[k + 1] - wk * (ph - cj)) * itp;
-        GS* const pk = pl.g[k];
-        GS* const pk1 = pl.g[k + 1];
-        if constexpr (PAR == 0) {
-          *plane_at<OFF32>(pk1, idx) = (GS)ga;
-          *plane_at<OFF32>(pk, idx) = (GS)gb;
-        } else {
-          *plane_at<OFF32>(pk, (unsigned)nb(cx, cy, cz)) = (GS)ga;
-          *plane_at<OFF32>(pk1, (unsigned)nb(-cx, -cy, -cz)) = (GS)gb;
-        }
-      }
-    } else if (macro) {
-      // dry evaluation: macroscopic fields of the current state
-      macro[idx] = ps;
-      macro[S + idx] = rho;
-#pragma unroll
-      for (int a = 0; a < DIM; ++a) {
-        macro[(2 + a) * S + idx] = u[a];
-        macro[(2 + DIM + a) * S + idx] = F[a];
-      }
-    }
-    if constexpr (MODE != MODE_STEP) {
-      const double dr = (double)rho;
-      acc[0] = (double)ps;
-      acc[1] = dr * (double)u[0];
-      acc[2] = dr * (double)u[1];
-      acc[3] = dr * (double)u[2];
-      const double sp2 = (double)u[0] * (double)u[0] + (double)u[1] * (double)u[1] + (double)u[2] * (double)u[2];
-      acc[4] = 0.5 * dr * sp2;
-      acc[5] = sqrt(sp2);
-      const bool fin = isfinite((double)ps) && isfinite(sp2);
-      acc[6] = fin ? 0.0 : 1.0;
-      if (!fin) acc[5] = 0.0;
-    }
-  }
+  if (valid) collide_cell<DIM, PAR, MODE, T, FS, GS, OFF32>(pl, phi, J, flags, geo, pp, nci_on, macro, x, y, z, acc);
   if constexpr (MODE != MODE_STEP) block_partials(acc, partials);
 }
 
 // ---------------------------------------------------------------------------
-// (c) diagnostics: sum phi and the Euler characteristic of the dispersed set
+// (c) diagnostics: sum phi and the number of droplets, i.e. the connected
+//     components of the dispersed set (8- / 26-connectivity, periodic)
 // ---------------------------------------------------------------------------
 
-// Euler characteristic of the union of closed voxels {fg}: each cell owns the
-// vertex at its (+1/2,+1/2,+1/2) corner, the three edges ending there from the
-// -x, -y, -z sides, the three faces on its +x, +y, +z sides and its own voxel.
+constexpr unsigned CC_NONE = 0xffffffffu;   // label of a cell outside the dispersed set
+
+// Labels are read with device-scope atomic loads: other workgroups, on other
+// XCDs, lower them while the merge kernel runs.
+__device__ __forceinline__ unsigned cc_load(const unsigned* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Root of the tree of x.  Every label is at most its own index and a root is
+// its own label, so the walk visits strictly decreasing indices and ends.  x is
+// then pointed at the root (an atomic minimum keeps labels monotone).
+__device__ __forceinline__ unsigned cc_find(unsigned* L, unsigned x) {
+  unsigned r = x, y;
+  while ((y = cc_load(L + r)) != r) r = y;
+  if (r != x) atomicMin(L + x, r);
+  return r;
+}
+
+// Joins the trees of cells a and b: the larger root is hung under the smaller
+// one by an atomic minimum.  If that root had meanwhile been hung elsewhere the
+// minimum returns its new parent and the join is retried from there; the larger
+// of the two roots strictly decreases on every retry.
+__device__ __forceinline__ void cc_unite(unsigned* L, unsigned a, unsigned b) {
+  while (true) {
+    a = cc_find(L, a);
+    b = cc_find(L, b);
+    if (a == b) return;
+    if (a > b) {
+      const unsigned t = a;
+      a = b;
+      b = t;
+    }
+    const unsigned old = atomicMin(L + b, a);
+    if (old == b) return;
+    b = old;
+  }
+}
+
+// L[idx] = idx for cells of the dispersed set, CC_NONE elsewhere.
 template <int DIM, typename T>
-__global__ __launch_bounds__(NT) void k_diag(const T* __restrict__ phi, Geo geo, int dispersed,
+__global__ __launch_bounds__(NT) void k_cc_init(const T* __restrict__ phi, Geo geo, int dispersed,
+                                                unsigned* __restrict__ L) {
+  int x, y, z;
+  block_cell(swizzled_block(), geo, x, y, z);
+  if (x >= geo.nx || y >= geo.ny) return;
+  const unsigned idx = (unsigned)Nbr(x, y, z, geo)(0, 0, 0);
+  const T v = phi[idx];
+  const bool in = dispersed ? (v > (T)0.5) : (v < (T)0.5);
+  L[idx] = in ? idx : CC_NONE;
+}
+
+// Every cell of the set joins its neighbours of the set at the 4 (2D) / 13 (3D)
+// offsets that precede it in (z, y, x) order; with the periodic wrap this
+// covers each adjacent pair once.
+template <int DIM>
+__global__ __launch_bounds__(NT) void k_cc_merge(Geo geo, unsigned* __restrict__ L) {
+  int x, y, z;
+  block_cell(swizzled_block(), geo, x, y, z);
+  if (x >= geo.nx || y >= geo.ny) return;
+  const Nbr nb(x, y, z, geo);
+  const unsigned idx = (unsigned)nb(0, 0, 0);
+  if (cc_load(L + idx) == CC_NONE) return;
+  const int dz0 = DIM == 3 ? -1 : 0;
+  for (int dz = dz0; dz <= 0; ++dz)
+    for (int dy = -1; dy <= (dz < 0 ? 1 : 0); ++dy)
+      for (int dx = -1; dx <= ((dz < 0 || dy < 0) ? 1 : -1); ++dx) {
+        const unsigned j = (unsigned)nb(dx, dy, dz);
+        if (cc_load(L + j) != CC_NONE) cc_unite(L, idx, j);
+      }
+}
+
+// Per-block partials of the diagnostics: [0] sum phi, [1] roots of the
+// component labels (one per droplet), [6] non-finite phi.
+template <int DIM, typename T>
+__global__ __launch_bounds__(NT) void k_diag(const T* __restrict__ phi, Geo geo,
+                                             const unsigned* __restrict__ L,
                                              double* __restrict__ partials) {
-  const int t = swizzled_block();
-  const int bx = t % geo.nbx, r = t / geo.nbx, by = r % geo.nby, z = r / geo.nby;
-  const int x = bx * BX + (int)(threadIdx.x & (BX - 1)), y = by * BY + (int)(threadIdx.x / BX);
+  int x, y, z;
+  block_cell(swizzled_block(), geo, x, y, z);
   double acc[NPART] = {0, 0, 0, 0, 0, 0, 0, 0};
   if (x < geo.nx && y < geo.ny) {
-    const Nbr nb(x, y, z, geo);
-    auto fg = [&](int dx, int dy, int dz) -> int {
-      const T v = phi[nb(dx, dy, dz)];
-      return dispersed ? (v > (T)0.5) : (v < (T)0.5);
-    };
-    const T p0 = phi[nb(0, 0, 0)];
+    const unsigned idx = (unsigned)Nbr(x, y, z, geo)(0, 0, 0);
+    const T p0 = phi[idx];
     acc[0] = (double)p0;
     acc[6] = isfinite((double)p0) ? 0.0 : 1.0;
-    int chi;
-    if (DIM == 2) {
-      const int b00 = fg(0, 0, 0), b10 = fg(1, 0, 0), b01 = fg(0, 1, 0), b11 = fg(1, 1, 0);
-      chi = (b00 | b10 | b01 | b11) - (b00 | b01) - (b00 | b10) + b00;
-    } else {
-      const int b000 = fg(0, 0, 0), b100 = fg(1, 0, 0), b010 = fg(0, 1, 0), b001 = fg(0, 0, 1);
-      const int b110 = fg(1, 1, 0), b101 = fg(1, 0, 1), b011 = fg(0, 1, 1), b111 = fg(1, 1, 1);
-      const int V = b000 | b100 | b010 | b001 | b110 | b101 | b011 | b111;
-      const int Ex = b000 | b010 | b001 | b011;
-      const int Ey = b000 | b100 | b001 | b101;
-      const int Ez = b000 | b100 | b010 | b110;
-      const int Fx = b000 | b100, Fy = b000 | b010, Fz = b000 | b001;
-      chi = V - (Ex + Ey + Ez) + (Fx + Fy + Fz) - b000;
-    }
-    acc[1] = (double)chi;
+    acc[1] = L[idx] == idx ? 1.0 : 0.0;
   }
   block_partials(acc, partials);
 }
@@ -880,7 +1025,7 @@ __global__ __launch_bounds__(NT) void k_init(FS* __restrict__ f, GS* __restrict_
   const T uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
 #pragma unroll
   for (int i = 0; i < H::Q; ++i) {
-    const T cu = (T)H::cx[i] * u[0] + (T)H::cy[i] * u[1] + (T)H::cz[i] * u[2];
+    const T cu = i == 0 ? (T)0 : sdot(H::cx[i], H::cy[i], H::cz[i], u[0], u[1], u[2]);
     const T fe = wt<H, T>(i) * (ps + (T)3 * cu + (T)4.5 * cu * cu - (T)1.5 * uu + (T)4.5 * cu * cu * cu -
                                (T)4.5 * cu * uu);
     Store<FS>::st(f + i * S + idx, fe, pp.fref[i]);
@@ -890,10 +1035,10 @@ __global__ __launch_bounds__(NT) void k_init(FS* __restrict__ f, GS* __restrict_
   const T ph = phi[idx];
   T gmag = m_sqrt(gr[0] * gr[0] + gr[1] * gr[1] + gr[2] * gr[2]);
   const T kc = pp.kc * ph * ((T)1 - ph) / (gmag + pp.eps_n);
+  const T jv[3] = {ph * u[0] + kc * gr[0], ph * u[1] + kc * gr[1], ph * u[2] + kc * gr[2]};
 #pragma unroll
   for (int k = 0; k < P::Q; ++k) {
-    const T cj = (T)P::cx[k] * (ph * u[0] + kc * gr[0]) + (T)P::cy[k] * (ph * u[1] + kc * gr[1]) +
-                 (T)P::cz[k] * (ph * u[2] + kc * gr[2]);
+    const T cj = k == 0 ? (T)0 : sdot(P::cx[k], P::cy[k], P::cz[k], jv[0], jv[1], jv[2]);
     g[k * S + idx] = (GS)(wt<P, T>(k) * (ph + cj * (T)P::inv_cs2));
   }
 }
@@ -938,6 +1083,107 @@ __global__ __launch_bounds__(NT) void k_setpop(FS* __restrict__ f, GS* __restric
   for (int i = 0; i < H::Q; ++i)
     Store<FS>::st(f + i * geo.S + e, (T)fi[i * N + e], pp.fref[i]);
   for (int k = 0; k < P::Q; ++k) g[k * geo.S + e] = (GS)gi[k * N + e];
+}
+
+// ---------------------------------------------------------------------------
+// multi-domain launches (serving): one grid covers every lattice of a batch
+// ---------------------------------------------------------------------------
+
+// One resident lattice in a batch.  The table lives in device memory; blocks
+// find their lattice by its first block index, and each lattice keeps its own
+// AA parity (step + s) so that lattices admitted at different times can share
+// one launch.  The per-cell code is the single-domain code, so every lattice
+// evolves bit for bit as it would alone.
+template <typename T, typename FS, typename GS>
+struct Job {
+  Planes<FS, GS> pl;
+  T* phi;
+  T* J;
+  unsigned* flags[2];
+  unsigned* list[2];
+  unsigned* cnt;      // [0], [1]: tile-list lengths per parity; [2]: cells with chi = 1
+  Geo geo;
+  PhysT<T> pp;
+  NciP np;
+  int nci_on;
+  T q_th;
+  int blk0, nblk;     // first block of this lattice in the batch grid, and its block count
+  long long step;     // completed steps of this lattice when the launch sequence starts
+};
+
+template <typename JT>
+__device__ __forceinline__ int find_job(const JT* __restrict__ jobs, int njobs, int t) {
+  int lo = 0, hi = njobs - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (jobs[mid].blk0 <= t) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+template <int DIM, typename T, typename FS, typename GS>
+__global__ __launch_bounds__(NT) void k_phi_multi(const Job<T, FS, GS>* __restrict__ jobs, int njobs,
+                                                  int s) {
+  const int t = swizzled_block();
+  const Job<T, FS, GS>& jb = jobs[find_job(jobs, njobs, t)];
+  const int lb = t - jb.blk0;
+  const int par = (int)((jb.step + s) & 1);
+  if (jb.nci_on && lb == 0 && threadIdx.x == 0) jb.cnt[2] = 0u;
+  int x, y, z;
+  block_cell(lb, jb.geo, x, y, z);
+  if (x >= jb.geo.nx || y >= jb.geo.ny) return;
+  if (par == 0)
+    phi_cell<DIM, 0, T, GS>(jb.pl.g[0], jb.phi, jb.geo, jb.flags[0], jb.list[0], jb.cnt, jb.nci_on,
+                            jb.q_th, x, y, z);
+  else
+    phi_cell<DIM, 1, T, GS>(jb.pl.g[0], jb.phi, jb.geo, jb.flags[1], jb.list[1], jb.cnt + 1,
+                            jb.nci_on, jb.q_th, x, y, z);
+}
+
+template <int DIM, typename T, typename FS, typename GS>
+__global__ __launch_bounds__(NT_NCI) void k_nci_multi(const Job<T, FS, GS>* __restrict__ jobs,
+                                                      int njobs, int s) {
+  __shared__ NciShared<DIM, T> sm;
+  for (int j = 0; j < njobs; ++j) {
+    const Job<T, FS, GS>& jb = jobs[j];
+    if (!jb.nci_on) continue;
+    const int par = (int)((jb.step + s) & 1);
+    nci_clear_other(jb.flags[1 - par], jb.list[1 - par], jb.cnt + (1 - par));
+    const unsigned ntiles = jb.cnt[par];
+    unsigned act = 0;
+    for (unsigned k = blockIdx.x; k < ntiles; k += gridDim.x)
+      nci_tile<DIM, T, false>(sm, jb.list[par][k], jb.phi, jb.J, nullptr, nullptr, jb.geo, jb.np, act);
+    act = wave_sum(act);
+    if ((threadIdx.x & 63) == 0 && act) atomicAdd(jb.cnt + 2, act);
+  }
+}
+
+template <int DIM, typename T, typename FS, typename GS, bool OFF32>
+__global__ __launch_bounds__(NT) void k_collide_multi(const Job<T, FS, GS>* __restrict__ jobs,
+                                                      int njobs, int s) {
+  const int t = swizzled_block();
+  const Job<T, FS, GS>& jb = jobs[find_job(jobs, njobs, t)];
+  const int lb = t - jb.blk0;
+  const int par = (int)((jb.step + s) & 1);
+  if (jb.nci_on && lb == 0 && threadIdx.x == 0) jb.cnt[1 - par] = 0u;
+  int x, y, z;
+  block_cell(lb, jb.geo, x, y, z);
+  if (x >= jb.geo.nx || y >= jb.geo.ny) return;
+  double acc[NPART];
+  if (par == 0)
+    collide_cell<DIM, 0, MODE_STEP, T, FS, GS, OFF32>(jb.pl, jb.phi, jb.J, jb.flags[0], jb.geo, jb.pp,
+                                                      jb.nci_on, nullptr, x, y, z, acc);
+  else
+    collide_cell<DIM, 1, MODE_STEP, T, FS, GS, OFF32>(jb.pl, jb.phi, jb.J, jb.flags[1], jb.geo, jb.pp,
+                                                      jb.nci_on, nullptr, x, y, z, acc);
+}
+
+// Advances the step counter of every lattice of the table (end of a replay).
+template <typename T, typename FS, typename GS>
+__global__ void k_advance(Job<T, FS, GS>* __restrict__ jobs, int njobs, int r) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < njobs) jobs[j].step += r;
 }
 
 }  // namespace lbm

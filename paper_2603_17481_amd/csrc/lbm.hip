@@ -50,7 +50,7 @@ struct Layout {
   long long N, S;
   int nblk, ntiles, ttx, tty, ttz, ntx, nty, ntz;
   size_t off_f, off_g, off_phi, off_J, off_flags, off_list, off_cnt, off_pa, off_pb, off_s1,
-      off_red, total;
+      off_red, off_lab, total;
 };
 
 bool valid_params(const lbm_params* p, std::string* why) {
@@ -109,6 +109,7 @@ Layout make_layout(const lbm_params* p) {
   L.off_pb = o;    o = align256(o + (size_t)L.nblk * NPART * 8);
   L.off_s1 = o;    o = align256(o + 2 * (size_t)RED1 * NPART * 8);
   L.off_red = o;   o = align256(o + (size_t)(HIST + 1) * 2 * NPART * 8);
+  L.off_lab = o;   o = align256(o + (size_t)L.N * 4);
   L.total = o;
   return L;
 }
@@ -151,6 +152,7 @@ struct lbm_ctx {
   double* pb() const { return (double*)(ws + L.off_pb); }
   double* s1(int k) const { return (double*)(ws + L.off_s1) + (size_t)k * RED1 * NPART; }
   double* red(int slot) const { return (double*)(ws + L.off_red) + (size_t)slot * 2 * NPART; }
+  unsigned* lab() const { return (unsigned*)(ws + L.off_lab); }   // component labels (diagnostics)
   bool nci_on() const { return p.a_rep > 0.0; }
   int fail(int code, const std::string& m) {
     err = m;
@@ -196,6 +198,58 @@ struct Timed {
     if (slot >= 0) (void)hipEventRecord(c->ev[2 * slot + 1], c->stream);
   }
 };
+
+// ---------------------------------------------------------------------------
+// Batches of lattices stepped together (serving)
+// ---------------------------------------------------------------------------
+
+constexpr int BATCH_R = 8;        // steps per captured graph replay
+constexpr int BATCH_CACHE = 8;    // cached batches (job tables and graphs)
+
+// Device job table, its pinned host mirror and the captured replay graph of one
+// ordered set of contexts.  A graph bakes the table pointer and the grid sizes;
+// the table contents (step counters) are re-uploaded before every call.
+struct Batch {
+  std::vector<lbm_ctx*> ctxs;
+  void* djobs = nullptr;
+  void* hjobs = nullptr;
+  size_t bytes = 0;
+  int total_blocks = -1;
+  bool o32 = false;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipEvent_t done = nullptr;     // end of the last call's work
+  hipEvent_t copied = nullptr;   // the last call's upload of the job table has run
+  bool used = false;
+  ~Batch() {
+    if (used && done) (void)hipEventSynchronize(done);   // no launch may still read the table
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (djobs) (void)hipFree(djobs);
+    if (hjobs) (void)hipHostFree(hjobs);
+    if (done) (void)hipEventDestroy(done);
+    if (copied) (void)hipEventDestroy(copied);
+  }
+};
+
+std::vector<Batch*>& batches() {
+  static std::vector<Batch*> b;
+  return b;
+}
+
+void forget_batches_of(const lbm_ctx* c) {
+  auto& bs = batches();
+  for (size_t i = 0; i < bs.size();) {
+    bool has = false;
+    for (lbm_ctx* x : bs[i]->ctxs) has |= (x == c);
+    if (has) {
+      delete bs[i];
+      bs.erase(bs.begin() + (long)i);
+    } else {
+      ++i;
+    }
+  }
+}
 
 // ---------------------------------------------------------------------------
 // Typed launch sequences
@@ -304,8 +358,11 @@ struct Engine {
 
   static void diag_finish(lbm_ctx* c, int slot) {
     Timed tm(c, 3);
+    hipLaunchKernelGGL((k_cc_init<DIM, T>), rows(c), dim3(NT), 0, c->stream, (const T*)c->phi(), c->geo,
+                       c->dispersed, c->lab());
+    hipLaunchKernelGGL((k_cc_merge<DIM>), rows(c), dim3(NT), 0, c->stream, c->geo, c->lab());
     hipLaunchKernelGGL((k_diag<DIM, T>), rows(c), dim3(NT), 0, c->stream, (const T*)c->phi(), c->geo,
-                       c->dispersed, c->pb());
+                       (const unsigned*)c->lab(), c->pb());
     const int chunk = (c->L.nblk + RED1 - 1) / RED1;
     hipLaunchKernelGGL(k_reduce_stage, dim3(RED1), dim3(NT), 0, c->stream, (const double*)c->pa(),
                        c->L.nblk, chunk, c->s1(0));
@@ -483,6 +540,108 @@ struct Engine {
     HIP_OR_FAIL(c, hipMemcpyAsync(r, c->red(0), sizeof(r), hipMemcpyDeviceToHost, c->stream));
     HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
     fill_diag(r, c->step, out);
+    return LBM_OK;
+  }
+
+  // ---- serving: several lattices advanced by multi-domain launches
+  using JobT = Job<T, FS, GS>;
+
+  static void batch_launch(hipStream_t st, const JobT* dj, int nj, int blocks, int s, bool o32) {
+    hipLaunchKernelGGL((k_phi_multi<DIM, T, FS, GS>), dim3((unsigned)blocks), dim3(NT), 0, st, dj, nj, s);
+    hipLaunchKernelGGL((k_nci_multi<DIM, T, FS, GS>), dim3(NCI_GRID), dim3(NT_NCI), 0, st, dj, nj, s);
+    if (o32)
+      hipLaunchKernelGGL((k_collide_multi<DIM, T, FS, GS, true>), dim3((unsigned)blocks), dim3(NT), 0, st,
+                         dj, nj, s);
+    else
+      hipLaunchKernelGGL((k_collide_multi<DIM, T, FS, GS, false>), dim3((unsigned)blocks), dim3(NT), 0,
+                         st, dj, nj, s);
+  }
+
+  static int batch(lbm_ctx* const* cs, int count, int n) {
+    lbm_ctx* c0 = cs[0];
+    hipStream_t st = c0->stream;
+    for (int i = 1; i < count; ++i) HIP_OR_FAIL(c0, hipStreamSynchronize(cs[i]->stream));
+    // find or create the cached batch of this ordered set of contexts
+    Batch* B = nullptr;
+    for (Batch* b : batches())
+      if ((int)b->ctxs.size() == count && std::equal(b->ctxs.begin(), b->ctxs.end(), cs)) B = b;
+    if (!B) {
+      if ((int)batches().size() >= BATCH_CACHE) {
+        delete batches().front();
+        batches().erase(batches().begin());
+      }
+      B = new Batch();
+      B->ctxs.assign(cs, cs + count);
+      B->bytes = sizeof(JobT) * (size_t)count;
+      if (hipMalloc(&B->djobs, B->bytes) != hipSuccess || hipHostMalloc(&B->hjobs, B->bytes) != hipSuccess ||
+          hipEventCreateWithFlags(&B->done, hipEventDisableTiming) != hipSuccess ||
+          hipEventCreateWithFlags(&B->copied, hipEventDisableTiming) != hipSuccess) {
+        delete B;
+        return c0->fail(LBM_E_OOM, "batch table allocation failed");
+      }
+      batches().push_back(B);
+    }
+    // the job table of this call; the pinned mirror is rewritten only once the
+    // previous call's upload from it has executed
+    if (B->used) HIP_OR_FAIL(c0, hipEventSynchronize(B->copied));
+    JobT* hj = (JobT*)B->hjobs;
+    int blocks = 0;
+    bool o32 = true;
+    for (int i = 0; i < count; ++i) {
+      lbm_ctx* c = cs[i];
+      JobT jb{};
+      jb.pl = planes(c);
+      jb.phi = (T*)c->phi();
+      jb.J = (T*)c->J();
+      for (int k = 0; k < 2; ++k) {
+        jb.flags[k] = c->flags(k);
+        jb.list[k] = c->list(k);
+      }
+      jb.cnt = c->cnt();
+      jb.geo = c->geo;
+      jb.pp = physT(c);
+      jb.np = c->nci;
+      jb.nci_on = c->nci_on() ? 1 : 0;
+      jb.q_th = (T)c->p.q_th;
+      jb.blk0 = blocks;
+      jb.nblk = c->L.nblk;
+      jb.step = c->step;
+      blocks += c->L.nblk;
+      o32 = o32 && off32(c);
+      hj[i] = jb;
+    }
+    HIP_OR_FAIL(c0, hipMemcpyAsync(B->djobs, B->hjobs, B->bytes, hipMemcpyHostToDevice, st));
+    HIP_OR_FAIL(c0, hipEventRecord(B->copied, st));
+    B->used = true;
+    const JobT* dj = (const JobT*)B->djobs;
+    const int full = n / BATCH_R, rem = n % BATCH_R;
+    if (full > 0) {
+      if (!B->exec || B->total_blocks != blocks || B->o32 != o32) {
+        if (B->exec) (void)hipGraphExecDestroy(B->exec);
+        if (B->graph) (void)hipGraphDestroy(B->graph);
+        B->exec = nullptr;
+        B->graph = nullptr;
+        HIP_OR_FAIL(c0, hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+        for (int sidx = 0; sidx < BATCH_R; ++sidx) batch_launch(st, dj, count, blocks, sidx, o32);
+        hipLaunchKernelGGL((k_advance<T, FS, GS>), dim3((count + 63) / 64), dim3(64), 0, st,
+                           (JobT*)B->djobs, count, BATCH_R);
+        HIP_OR_FAIL(c0, hipStreamEndCapture(st, &B->graph));
+        HIP_OR_FAIL(c0, hipGraphInstantiate(&B->exec, B->graph, nullptr, nullptr, 0));
+        B->total_blocks = blocks;
+        B->o32 = o32;
+      }
+      for (int k = 0; k < full; ++k) HIP_OR_FAIL(c0, hipGraphLaunch(B->exec, st));
+    }
+    for (int sidx = 0; sidx < rem; ++sidx) batch_launch(st, dj, count, blocks, sidx, o32);
+    if (rem)
+      hipLaunchKernelGGL((k_advance<T, FS, GS>), dim3((count + 63) / 64), dim3(64), 0, st,
+                         (JobT*)B->djobs, count, rem);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return c0->fail(LBM_E_HIP, std::string("batch launch: ") + hipGetErrorString(e));
+    for (int i = 0; i < count; ++i) cs[i]->step += n;
+    // later work on the other contexts' streams waits for the batch
+    HIP_OR_FAIL(c0, hipEventRecord(B->done, st));
+    for (int i = 1; i < count; ++i) HIP_OR_FAIL(c0, hipStreamWaitEvent(cs[i]->stream, B->done, 0));
     return LBM_OK;
   }
 };
@@ -665,6 +824,7 @@ int lbm_create(const lbm_params* p, void* dev_workspace, size_t ws_bytes, void* 
 void lbm_destroy(lbm_ctx* c) {
   if (!c) return;
   if (c->stream) (void)hipStreamSynchronize(c->stream);
+  forget_batches_of(c);
   for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
   if (c->own_ws && c->ws) (void)hipFree(c->ws);
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
@@ -904,11 +1064,19 @@ int lbm_kernel_times(lbm_ctx* c, double* ms, long* counts) {
 
 int lbm_batch_step(lbm_ctx* const* ctxs, int count, int n) {
   if (!ctxs || count < 0 || n < 0) return LBM_E_INVALID;
+  if (count == 0 || n == 0) return LBM_OK;
+  lbm_ctx* c0 = ctxs[0];
+  if (!c0) return LBM_E_INVALID;
   for (int i = 0; i < count; ++i) {
-    const int rc = lbm_step(ctxs[i], n);
-    if (rc != LBM_OK) return rc;
+    lbm_ctx* c = ctxs[i];
+    if (!c) return c0->fail(LBM_E_INVALID, "null context in batch");
+    if (!c->initialised) return c0->fail(LBM_E_STATE, "batch holds an uninitialised context");
+    if (c->dev != c0->dev || c->p.dim != c0->p.dim || c->p.precision != c0->p.precision)
+      return c0->fail(LBM_E_INVALID, "batch contexts must share device, dimension and precision");
+    for (int j = 0; j < i; ++j)
+      if (ctxs[j] == c) return c0->fail(LBM_E_INVALID, "context listed twice in batch");
   }
-  return LBM_OK;
+  return dispatch(c0, [&](auto E) { return decltype(E)::batch(ctxs, count, n); });
 }
 
 }  // extern "C"

@@ -25,11 +25,12 @@ def test_default_params_match_paper_values():
 
 
 def test_workspace_bytes_model():
-    # 3D FP32: 19 + 7 populations, phi and J, each a plane of N floats (plus small scratch)
+    # 3D FP32: 19 + 7 populations, phi and J, each a plane of N floats, plus one
+    # 32-bit component label per cell for the droplet count (and small scratch)
     p = W.Params(dim=3, nx=512, ny=512, nz=512, precision="fp32")
     n = p.n_cells
     b = L.lbm_workspace_bytes(p)
-    assert 4 * n * (19 + 7 + 1 + 3) <= b < 4 * n * (19 + 7 + 1 + 3) * 1.02
+    assert 4 * n * (19 + 7 + 1 + 3 + 1) <= b < 4 * n * (19 + 7 + 1 + 3 + 1) * 1.02
     p16 = p.replace(precision="fp16")
     b16 = L.lbm_workspace_bytes(p16)
     assert b - b16 >= 2 * n * 19 * 0.99

@@ -263,3 +263,55 @@ def test_save_load_continues_bit_for_bit():
     assert b.step_count == 33
     b.step(40)
     assert np.array_equal(a.phi(), b.phi()) and np.array_equal(a.u(), b.u())
+
+
+def _shapes_phi(p, seed):
+    """A field whose dispersed set has holes and wraps the periodic box: a ring
+    (2D) or spherical shell (3D) with a droplet inside its hole, a band that
+    wraps around x, and seeded random overlapping blobs."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    shape = p.shape
+    grids = np.meshgrid(*[np.arange(n, dtype=np.float64) for n in shape], indexing="ij")
+    X = grids[::-1]                        # x, y(, z) arrays indexed [z][y][x] / [y][x]
+    ns = (p.nx, p.ny, p.nz)[: p.dim]
+
+    def r_to(c):
+        r2 = 0.0
+        for a in range(p.dim):
+            d = X[a] - c[a]
+            d -= ns[a] * np.round(d / ns[a])
+            r2 = r2 + d * d
+        return np.sqrt(r2)
+
+    c0 = [0.3 * n + 0.37 for n in ns]
+    r = r_to(c0)
+    dist = np.minimum(12.0 - r, r - 6.0)                     # ring / shell, thickness 6
+    dist = np.maximum(dist, 2.5 - r)                         # droplet in its hole
+    dist = np.maximum(dist, 2.5 - np.abs(X[1] - 0.8 * ns[1]))   # band wrapping around x
+    for _ in range(5):
+        c = [rng.uniform(0, n) for n in ns]
+        dist = np.maximum(dist, rng.uniform(2.0, 5.0) - r_to(c))
+    return 0.5 * (1.0 + np.tanh(2.0 * dist / p.width))
+
+
+@pytest.mark.parametrize("dim,dispersed", [(2, 1), (3, 1), (3, 0)])
+@pytest.mark.parametrize("seed", [1, 2])
+def test_droplet_count_equals_bfs(dim, dispersed, seed):
+    """The device droplet count (union-find) equals the oracle's breadth-first
+    count on the same field, also for sets with holes (where an Euler
+    characteristic would not count components) and sets that wrap the box."""
+    if dim == 2:
+        p = W.Params(dim=2, nx=96, ny=80, width=3.0, precision="fp64", dispersed=dispersed)
+    else:
+        p = W.Params(dim=3, nx=56, ny=48, nz=40, width=3.0, precision="fp64", dispersed=dispersed)
+    phi = _shapes_phi(p, seed)
+    if dispersed == 0:
+        phi = 1.0 - phi
+    announce(f"droplet count {dim}D dispersed={dispersed} seed={seed}")
+    g = L.Lattice(p)
+    g.init_fields(phi)
+    n_gpu = g.diagnostics()["n_droplets"]
+    n_bfs = O.count_components(p, g.phi(), dispersed)
+    print(f"[gpu-case] components gpu {n_gpu} bfs {n_bfs}", flush=True)
+    assert n_gpu == n_bfs >= 3
+    g.close()
