@@ -46,15 +46,24 @@ def kernel_hash() -> str:
     return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
 
 
-def traffic_from_profile(n_cells):
-    """HBM bytes per collide launch from the committed rocprofv3 counter summary,
-    or None when it is missing or was taken on another version of the kernels."""
+def workload_key(args) -> str:
+    return (f"{args.workload} n={args.n} bubbles={args.bubbles} r={args.rmin:g}-{args.rmax:g} "
+            f"gap={args.gap:g} {args.precision}")
+
+
+def traffic_from_profile(args):
+    """HBM bytes per step of the collide kernel from the committed rocprofv3
+    counter summary, or None when it is missing, was taken on another workload
+    or on another version of the kernels."""
     if not os.path.exists(COUNTERS):
         return None
     txt = open(COUNTERS).read()
     m_hash = re.search(r"kernel source sha256\[:16\]: ([0-9a-f]+)", txt)
+    m_key = re.search(r"workload key: (.+)", txt)
     m_bytes = re.search(r"hbm bytes per launch: ([0-9.eE+]+)", txt)
-    if not m_hash or not m_bytes or m_hash.group(1) != kernel_hash():
+    if not m_hash or not m_bytes or not m_key or m_hash.group(1) != kernel_hash():
+        return None
+    if m_key.group(1).strip() != workload_key(args):
         return None
     return float(m_bytes.group(1))
 
@@ -62,10 +71,11 @@ def traffic_from_profile(n_cells):
 def make_workload(args):
     from paper_2603_17481_amd import workloads as W
     if args.workload == "swarm":
-        st = W.config_swarm(n=args.n, bubbles=args.bubbles, precision=args.precision)
-        desc = (f"bubble swarm {args.n}^3 periodic, D3Q19+D3Q7, {args.bubbles} bubbles R~U[8,12] "
-                f"gap 3 (seed 3), g=1e-6 -z, density ratio 10, W=5, sigma=5e-3, A_rep=5e-3, "
-                f"{args.precision}, diagnostics every {args.diag} steps")
+        st = W.config_swarm(n=args.n, bubbles=args.bubbles, rmin=args.rmin, rmax=args.rmax, gap=args.gap,
+                            precision=args.precision)
+        desc = (f"bubble swarm {args.n}^3 periodic, D3Q19+D3Q7, {args.bubbles} bubbles "
+                f"R~U[{args.rmin:g},{args.rmax:g}] gap {args.gap:g} (seed 3), g=1e-6 -z, density ratio 10, "
+                f"W=5, sigma=5e-3, A_rep=5e-3, {args.precision}, diagnostics every {args.diag} steps")
     else:
         st = W.config_collision_3d(precision=args.precision)
         desc = f"droplet collision 256x128x128, D3Q19+D3Q7, {args.precision}"
@@ -80,7 +90,7 @@ def cpu_baseline(args):
     from paper_2603_17481_amd import workloads as W
     n = args.cpu_n
     bubbles = max(1, int(round(args.bubbles * (n / args.n) ** 3)))
-    st = W.config_swarm(n=n, bubbles=bubbles, precision="fp64")
+    st = W.config_swarm(n=n, bubbles=bubbles, rmin=args.rmin, rmax=args.rmax, gap=args.gap, precision="fp64")
     o = Oracle(st.params)
     o.init_fields(st.phi, st.u)
     o.step(1)
@@ -94,6 +104,26 @@ def cpu_baseline(args):
                       f"{dt:.1f} s"}
 
 
+def serving_report(args):
+    """The served stream: 64 collision / swarm jobs in cubic boxes 64^3..192^3,
+    Poisson arrivals at 4 jobs/s, 5000 steps each, FP32, continuous batching
+    with 16 slots under two HBM budgets (the free device memory and a binding
+    4 GiB); beside it one-job-at-a-time serving of the same arrivals."""
+    from paper_2603_17481_amd import serving as S
+    log = lambda m: print(m, file=sys.stderr, flush=True)
+    jobs = S.make_jobs(count=args.serve_jobs, rate=4.0, steps=args.serve_steps, seed=4)
+    rep = {"workload": f"{len(jobs)} jobs (collision / swarm, boxes 64^3..192^3 step 32), Poisson 4 jobs/s "
+                       f"(seed 4), {args.serve_steps} steps each, FP32, 16 slots, rounds of 200 steps"}
+    for name, budget in (("batched", S.default_budget()), ("batched_4GiB", 4 << 30)):
+        log(f"[bench] serving {len(jobs)} jobs, HBM budget {budget / 2**30:.1f} GiB")
+        rep[name] = S.serve_batched(jobs, budget, max_slots=16, round_steps=200)
+        log(f"[bench] {name}: {rep[name]}")
+    if args.serving == "full":
+        rep["one_at_a_time"] = S.serve_fifo(jobs)
+    rep["one_at_a_time_model"] = S.model_fifo(jobs, S.measure_alone(jobs, log=log))
+    return rep
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -102,11 +132,19 @@ def main():
     ap.add_argument("--workload", default="swarm", choices=["swarm", "collision"])
     ap.add_argument("--n", type=int, default=512)
     ap.add_argument("--bubbles", type=int, default=400)
+    ap.add_argument("--rmin", type=float, default=8.0)
+    ap.add_argument("--rmax", type=float, default=12.0)
+    ap.add_argument("--gap", type=float, default=3.0)
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp16", "bf16", "fp64"])
     ap.add_argument("--diag", type=int, default=100)
     ap.add_argument("--cpu-n", type=int, default=96)
     ap.add_argument("--cpu-steps", type=int, default=60)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serving", default="batched", choices=["batched", "full", "off"],
+                    help="served job stream: batched serving measured, one-at-a-time serving from a "
+                         "queue model of measured alone step times ('batched'), or also measured ('full')")
+    ap.add_argument("--serve-jobs", type=int, default=64)
+    ap.add_argument("--serve-steps", type=int, default=5000)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a plain 2 GiB device copy first (reference for HBM counters)")
     args = ap.parse_args()
@@ -149,7 +187,7 @@ def main():
     torch.cuda.empty_cache()
     stream = torch.cuda.Stream()
     lat = lbm.Lattice(p, stream=stream)
-    lat.init_fields(st.phi, st.u)
+    lat.init_fields(st.phi, None if not np.any(st.u) else st.u)   # the swarm starts at rest
     del st
     lat.step(args.warmup)
     lat.sync()
@@ -188,7 +226,7 @@ def main():
     coll_ms, coll_n = kt["collide"]
     avg_s = coll_ms / coll_n / 1e3
     achieved = bytes_launch / avg_s / 1e9
-    traffic = traffic_from_profile(N)
+    traffic = traffic_from_profile(args)
     diag = lat.diagnostics()
     out = {
         "metric": METRIC,
@@ -217,6 +255,11 @@ def main():
         "state": {"step": diag["step"], "n_bubbles": diag["n_droplets"], "nci_active": diag["nci_active"],
                   "finite": diag["finite"], "mass_phi": diag["mass_phi"]},
     }
+    lat.close()
+    del lat
+    torch.cuda.empty_cache()
+    if args.serving != "off":
+        out["serving"] = serving_report(args)
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(args)

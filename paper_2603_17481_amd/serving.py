@@ -19,7 +19,6 @@ import argparse
 import concurrent.futures as cf
 import hashlib
 import json
-import math
 import sys
 import time
 from dataclasses import dataclass, field
@@ -58,7 +57,7 @@ def make_jobs(count: int = 64, rate: float = 4.0, steps: int = 5000, seed: int =
     """Seeded job stream: Poisson arrivals (exponential gaps of mean 1/rate),
     kind collision or swarm with equal odds, box edge uniform over `sizes`,
     collision relative speed U[0.02, 0.08] and impact parameter U[0, 0.6] R,
-    swarm bubble count U{10..50} (capped so the gas fraction stays <= 20 %)."""
+    swarm bubble count uniform over 10..50."""
     rng = np.random.Generator(np.random.PCG64(seed))
     t = 0.0
     jobs = []
@@ -72,9 +71,7 @@ def make_jobs(count: int = 64, rate: float = 4.0, steps: int = 5000, seed: int =
             spec.speed = float(rng.uniform(0.02, 0.08))
             spec.impact = float(rng.uniform(0.0, 0.6))
         else:
-            drawn = int(rng.integers(10, 51))
-            mean_vol = 4.0 / 3.0 * math.pi * 8.0 ** 3
-            spec.bubbles = max(1, min(drawn, int(0.2 * n ** 3 / mean_vol)))
+            spec.bubbles = int(rng.integers(10, 51))
         jobs.append(spec)
     return jobs
 
@@ -90,15 +87,16 @@ def job_params(spec: JobSpec) -> W.Params:
 
 
 def job_state(spec: JobSpec) -> W.InitialState:
-    """Initial fields: a droplet pair of radius n/8 whose centres start n/2 apart
-    along x (offset across by the impact parameter), or a seeded Poisson-disk
-    bubble swarm with radii U[6, 10] and surface gap 2."""
+    """Initial fields: two droplets of radius R = n/8 whose centres start 2.5 R
+    apart along x (offset across by the impact parameter), approaching with the
+    relative speed split evenly; or a seeded Poisson-disk bubble swarm with radii
+    U[max(5, n/16), n/10] and surface gap 3."""
     p = job_params(spec)
     if spec.kind == "collision":
         r = spec.n / 8.0
-        return W.droplet_pair(p, radius=r, separation=spec.n / 2.0, speed=spec.speed / 2.0,
+        return W.droplet_pair(p, radius=r, separation=2.5 * r, speed=spec.speed / 2.0,
                               offset=spec.impact * r)
-    return W.bubble_swarm(p, spec.bubbles, 6.0, 10.0, 2.0, spec.seed)
+    return W.bubble_swarm(p, spec.bubbles, max(5.0, spec.n / 16.0), spec.n / 10.0, 3.0, spec.seed)
 
 
 def job_bytes(spec: JobSpec) -> int:
@@ -277,6 +275,47 @@ def serve_fifo(jobs: List[JobSpec], log=None) -> dict:
     return _report("one_at_a_time", jobs, finished, now())
 
 
+def measure_alone(jobs: List[JobSpec], probe_steps: int = 200, log=None) -> Dict[tuple, dict]:
+    """Per (kind, box) class of the stream: seconds per step of one representative
+    job run alone with lbm_step (after a short warm-up), and its preparation time."""
+    out = {}
+    for spec in jobs:
+        key = (spec.kind, spec.n)
+        if key in out:
+            continue
+        t0 = time.perf_counter()
+        lat = _prepare(spec)
+        prep = time.perf_counter() - t0
+        lat.step(16)
+        lat.sync()
+        t1 = time.perf_counter()
+        lat.step(probe_steps)
+        lat.sync()
+        out[key] = {"step_s": (time.perf_counter() - t1) / probe_steps, "prep_s": prep}
+        lat.close()
+        if log:
+            log(f"[alone] {key}: {out[key]['step_s'] * 1e3:.3f} ms/step, prep {prep:.2f} s")
+    return out
+
+
+def model_fifo(jobs: List[JobSpec], alone: Dict[tuple, dict]) -> dict:
+    """One-job-at-a-time serving of the same arrivals as a queue model: job j
+    starts when it has arrived and job j-1 has finished, and runs for its steps
+    times the measured alone step time; a job that finds the server idle first
+    waits for its own preparation (otherwise that overlaps the previous run)."""
+    t_free = 0.0
+    runs = []
+    for spec in sorted(jobs, key=lambda j: j.arrival):
+        a = alone[(spec.kind, spec.n)]
+        start = max(spec.arrival + a["prep_s"], t_free) if spec.arrival >= t_free else t_free
+        t_free = start + spec.steps * a["step_s"]
+        r = Running(spec, finished=t_free, diag={"finite": True})
+        runs.append(r)
+    out = _report("one_at_a_time_model", jobs, runs, t_free)
+    out.pop("outcomes_finite")
+    return out
+
+
 def default_budget(reserve_bytes: int = 16 << 30) -> int:
     import torch
     free, _ = torch.cuda.mem_get_info()
@@ -293,6 +332,8 @@ def main(argv=None):
     ap.add_argument("--round-steps", type=int, default=200)
     ap.add_argument("--budget-gib", type=float, default=0.0, help="HBM budget (0: free memory - 16 GiB)")
     ap.add_argument("--no-fifo", action="store_true")
+    ap.add_argument("--model-fifo", action="store_true",
+                    help="also give the one-at-a-time queue model from measured alone step times")
     args = ap.parse_args(argv)
     import torch
     assert torch.cuda.is_available(), "serving needs a GPU"
@@ -302,6 +343,8 @@ def main(argv=None):
     out = {"batched": serve_batched(jobs, budget, args.slots, args.round_steps, log=log)}
     if not args.no_fifo:
         out["one_at_a_time"] = serve_fifo(jobs, log=log)
+    if args.model_fifo:
+        out["one_at_a_time_model"] = model_fifo(jobs, measure_alone(jobs, log=log))
     print(json.dumps(out), flush=True)
 
 

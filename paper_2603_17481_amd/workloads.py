@@ -202,29 +202,36 @@ def bubble_swarm(p: Params, count: int, rmin: float, rmax: float, gap: float, se
 
 def _union_fast(p: Params, spheres: Sequence[Sphere], inside_liquid: bool) -> InitialState:
     """Same field as spheres_state, evaluated sphere by sphere on bounding boxes
-    (needed for large boxes with many spheres)."""
+    (needed for large boxes with many spheres).  Squared distances are formed
+    per axis and summed in x, y, z order, as spheres_state does."""
     dist = np.full(p.shape, -1e30)
     ns = (p.nx, p.ny, p.nz)
     reach = p.width * 4.0
     for s in spheres:
-        lo, hi, idx = [], [], []
+        idx, contiguous = [], True
         for a in range(p.dim):
             lo_a = int(math.floor(s.center[a] - s.radius - reach))
             hi_a = int(math.ceil(s.center[a] + s.radius + reach))
             span = np.arange(lo_a, hi_a + 1)
             if len(span) >= ns[a]:
                 span = np.arange(ns[a])
-            idx.append(np.unique(np.mod(span, ns[a])))
-        grids = np.meshgrid(*[i.astype(np.float64) for i in idx], indexing="ij")
-        r2 = np.zeros(grids[0].shape)
-        for a in range(p.dim):
-            d = _min_image(grids[a] - s.center[a], ns[a])
-            r2 += d * d
+            ia = np.unique(np.mod(span, ns[a]))
+            contiguous &= bool(ia[-1] - ia[0] + 1 == len(ia))
+            idx.append(ia)
+        d2 = [_min_image(idx[a].astype(np.float64) - s.center[a], ns[a]) ** 2 for a in range(p.dim)]
+        if p.dim == 3:
+            r2 = d2[0][None, None, :] + d2[1][None, :, None]
+            r2 = r2 + d2[2][:, None, None]
+        else:
+            r2 = d2[0][None, :] + d2[1][:, None]
         d_s = s.radius - np.sqrt(r2)
         # arrays are indexed (z, y, x) / (y, x): reverse the axis order
-        ix = np.ix_(*idx[::-1])
-        sub = dist[ix]
-        dist[ix] = np.maximum(sub, np.transpose(d_s))
+        if contiguous:
+            view = dist[tuple(slice(int(ia[0]), int(ia[-1]) + 1) for ia in idx[::-1])]
+            np.maximum(view, d_s, out=view)
+        else:
+            ix = np.ix_(*idx[::-1])
+            dist[ix] = np.maximum(dist[ix], d_s)
     dist = np.where(dist < -1e29, -1e3, dist)
     if not inside_liquid:
         dist = -dist
