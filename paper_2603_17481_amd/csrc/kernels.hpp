@@ -226,6 +226,15 @@ __device__ __forceinline__ T wave_max(T v) {
   }
   return v;
 }
+template <typename T>
+__device__ __forceinline__ T wave_min(T v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    T u = __shfl_xor(v, o, 64);
+    v = u < v ? u : v;
+  }
+  return v;
+}
 
 // ---------------------------------------------------------------------------
 // (a1) phi moment of the phase-field populations
@@ -308,14 +317,13 @@ __device__ __forceinline__ void group_min(int& d2, T& dot) {
   }
 }
 
-// Per listed tile: (1) phi with a halo of 4 into LDS; (2) q on tile + 3 and
-// n only where q >= q_th (n is read only after a candidate passes the gate);
-// (3) the gated cells of the tile are listed; (4) each gated cell gets an
-// 8-lane group whose lanes scan one window plane each (dz in 3D, dy in 2D):
-// pass 0 finds the smallest |r|^2 and the smallest n(x).n(y) at it, pass 1 the
-// first candidate in scan order within tie_eps of that dot; the planes are
-// combined with wave shuffles; (5) the group leader builds J (Sec. 2.3.3) and
-// the tile's J is written from LDS, zero for cells without a partner.
+// Normal and indicator of one cell of the near-contact region, read as one
+// 16-byte (FP32) / 32-byte (FP64) LDS access.
+template <typename T>
+struct alignas(4 * sizeof(T)) NQ {
+  T n0, n1, n2, q;
+};
+
 template <int DIM, typename T>
 struct NciShared {
   using TL = NciTile<DIM, T>;
@@ -323,13 +331,21 @@ struct NciShared {
   static constexpr int PX = TX + 2 * PHI_HALO, PY = TY + 2 * PHI_HALO, PZ = DIM == 3 ? TZ + 2 * PHI_HALO : 1;
   static constexpr int NX = TX + 2 * NQ_HALO, NY = TY + 2 * NQ_HALO, NZ = DIM == 3 ? TZ + 2 * NQ_HALO : 1;
   static constexpr int NPH = PX * PY * PZ, NNQ = NX * NY * NZ;
-  T phs[NPH];
-  T nqs[DIM + 1][NNQ];
+  struct Out {
+    T gJ[TC][DIM];   // result per gated cell
+    int gpart[TC];   // packed partner offset + 1 (0: no partner)
+  };
+  union {
+    T phs[NPH];      // phi tile with halo (steps 1-2)
+    Out out;         // results (steps 4-6)
+  };
+  NQ<T> nq[NNQ];
   short glist[TC];   // gated tile cells
   short gslot[TC];   // tile cell -> index in glist, or -1
-  T gJ[TC][DIM];     // result per gated cell
-  int gpart[TC];     // packed partner offset + 1 (0: no partner)
+  T red[NT_NCI / 64][3];
+  T mhat[3];
   int ng;
+  int skip;
 };
 
 // Clears the tile flags of the other AA parity (set by the previous step) so
@@ -343,14 +359,16 @@ __device__ __forceinline__ void nci_clear_other(unsigned* __restrict__ flags_oth
 }
 
 // Per listed tile: (1) phi with a halo of 4 into LDS; (2) q on tile + 3 and
-// n only where q >= q_th (n is read only after a candidate passes the gate);
-// (3) the gated cells of the tile are listed; (4) each gated cell gets an
-// 8-lane group whose lanes scan one window plane each (dz in 3D, dy in 2D):
-// pass 0 finds the smallest |r|^2 and the smallest n(x).n(y) at it, pass 1 the
-// first candidate in scan order within tie_eps of that dot; the planes are
-// combined with wave shuffles; (5) the group leader builds J (Sec. 2.3.3) and
-// the tile's J is written from LDS, zero for cells without a partner.
-template <int DIM, typename T, bool DEBUG>
+// n where q >= q_th, packed with q; (3) the gated cells of the tile are listed;
+// (4) each gated cell gets an 8-lane group whose lanes scan one window plane
+// each (dz in 3D, dy in 2D), the window radius WR being a compile-time
+// constant so that the scan is unrolled and its LDS reads use immediate
+// offsets: pass 0 finds the smallest |r|^2 and the smallest n(x).n(y) at it,
+// pass 1 (only where a partner exists) the first candidate in scan order
+// within tie_eps of that dot; the planes are combined with wave shuffles;
+// (5) the group leader builds J (Sec. 2.3.3) and the tile's J is written from
+// LDS, zero for cells without a partner.
+template <int DIM, typename T, bool DEBUG, int WR>
 __device__ __forceinline__ void nci_tile(NciShared<DIM, T>& sm, unsigned t, const T* __restrict__ phi,
                                          T* __restrict__ J, int* __restrict__ chi_out,
                                          int* __restrict__ part_out, const Geo& geo, const NciP& np,
@@ -362,9 +380,9 @@ __device__ __forceinline__ void nci_tile(NciShared<DIM, T>& sm, unsigned t, cons
   constexpr int PX = NciShared<DIM, T>::PX, PY = NciShared<DIM, T>::PY;
   constexpr int NX = NciShared<DIM, T>::NX, NY = NciShared<DIM, T>::NY;
   constexpr int NPH = NciShared<DIM, T>::NPH, NNQ = NciShared<DIM, T>::NNQ;
+  static_assert(WR >= 1 && WR <= NQ_HALO, "window radius");
   const T q_th = (T)np.q_th, eta = (T)np.eta, cos_opp = (T)np.cos_opp, eps_n = (T)np.eps_n,
           eps_q = (T)np.eps_q, tie = (T)np.tie_eps;
-  const int w = np.w;
   const int lane8 = threadIdx.x & 7, grp = threadIdx.x >> 3;
   constexpr int NGRP = NT_NCI / 8;
   const int tx = (int)(t % (unsigned)geo.ntx);
@@ -381,14 +399,14 @@ __device__ __forceinline__ void nci_tile(NciShared<DIM, T>& sm, unsigned t, cons
   }
   __syncthreads();
   // (2) indicator everywhere on tile + 3, normal where the indicator passes the gate
+  T msum[3] = {0, 0, 0};
   for (int e = threadIdx.x; e < NNQ; e += NT_NCI) {
     const int ex = e % NX, ey = (e / NX) % NY, ez = e / (NX * NY);
     const int c = (ex + 1) + PX * ((ey + 1) + PY * (DIM == 3 ? ez + 1 : 0));
     const T ph = sm.phs[c];
     const T pc = ph < (T)0 ? (T)0 : (ph > (T)1 ? (T)1 : ph);
-    const T q = pc * ((T)1 - pc);
-    sm.nqs[DIM][e] = q;
-    if (q >= q_th) {
+    NQ<T> v{(T)0, (T)0, (T)0, pc * ((T)1 - pc)};
+    if (v.q >= q_th) {
       T gr[3], lap;
       grad_lap<DIM, T>([&](int i) { return sm.phs[c + L::cx[i] + PX * (L::cy[i] + PY * L::cz[i])]; },
                        gr, lap);
@@ -396,18 +414,63 @@ __device__ __forceinline__ void nci_tile(NciShared<DIM, T>& sm, unsigned t, cons
       if (DIM == 3) mag += gr[2] * gr[2];
       mag = m_sqrt(mag);
       const T den = mag + eps_n;
-#pragma unroll
-      for (int a = 0; a < DIM; ++a) sm.nqs[a][e] = gr[a] / den;
+      v.n0 = gr[0] / den;
+      v.n1 = gr[1] / den;
+      if (DIM == 3) v.n2 = gr[2] / den;
+      msum[0] += v.n0;
+      msum[1] += v.n1;
+      msum[2] += v.n2;
     }
+    sm.nq[e] = v;
   }
-  __syncthreads();
+  // (2b) can two normals of the region face each other?  With m the mean
+  // gated normal and c the smallest n.m/|m| over the gated cells, any two of
+  // them are at most 2 acos(c) apart, so n(x).n(y) >= 2c^2 - 1 (c >= 0).  When
+  // that bound exceeds cos_opp no cell of the tile can have a partner and the
+  // search is skipped (the tile's J is zero); a margin of 1e-3 covers rounding.
+  {
+    const int wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const T v = wave_sum(msum[a]);
+      if ((threadIdx.x & 63) == 0) sm.red[wv][a] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      T m[3] = {0, 0, 0};
+      for (int k = 0; k < NT_NCI / 64; ++k)
+        for (int a = 0; a < 3; ++a) m[a] += sm.red[k][a];
+      const T mm = m_sqrt(m[0] * m[0] + m[1] * m[1] + m[2] * m[2]);
+      for (int a = 0; a < 3; ++a) sm.mhat[a] = mm > (T)1e-6 ? m[a] / mm : (T)0;
+    }
+    __syncthreads();
+    const T mh[3] = {sm.mhat[0], sm.mhat[1], sm.mhat[2]};
+    T cmin = (T)1;
+    for (int e = threadIdx.x; e < NNQ; e += NT_NCI) {
+      const NQ<T> v = sm.nq[e];
+      if (v.q >= q_th) {
+        const T d = v.n0 * mh[0] + v.n1 * mh[1] + v.n2 * mh[2];
+        cmin = d < cmin ? d : cmin;
+      }
+    }
+    cmin = wave_min(cmin);
+    if ((threadIdx.x & 63) == 0) sm.red[wv][0] = cmin;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      T c = (T)1;
+      for (int k = 0; k < NT_NCI / 64; ++k) c = sm.red[k][0] < c ? sm.red[k][0] : c;
+      sm.skip = c >= (T)0 && (T)2 * c * c - (T)1 > cos_opp + (T)1e-3;
+    }
+    __syncthreads();
+  }
+  const bool skip = sm.skip != 0;
   // (3) list the gated cells of the tile
   for (int e = threadIdx.x; e < TC; e += NT_NCI) {
     const int lx = e % TX, ly = (e / TX) % TY, lz = e / (TX * TY);
     const bool inside = ox + lx < geo.nx && oy + ly < geo.ny && oz + lz < geo.nz;
     const int cc = (lx + NQ_HALO) + NX * ((ly + NQ_HALO) + NY * (DIM == 3 ? lz + NQ_HALO : 0));
     short slot = -1;
-    if (inside && sm.nqs[DIM][cc] >= q_th) {
+    if (!skip && inside && sm.nq[cc].q >= q_th) {
       slot = (short)atomicAdd(&sm.ng, 1);
       sm.glist[slot] = (short)e;
     }
@@ -416,66 +479,70 @@ __device__ __forceinline__ void nci_tile(NciShared<DIM, T>& sm, unsigned t, cons
   __syncthreads();
   const int ng = sm.ng;
   // (4) partner search, one 8-lane group per gated cell, one plane per lane
+  constexpr int ROWS = DIM == 3 ? 2 * WR + 1 : 1;   // window rows scanned per lane
   for (int base = 0; base < ng; base += NGRP) {
     const int gi = base + grp;
     const bool cell_ok = gi < ng;
     const int e = cell_ok ? sm.glist[gi] : 0;
     const int lx = e % TX, ly = (e / TX) % TY, lz = e / (TX * TY);
     const int cc = (lx + NQ_HALO) + NX * ((ly + NQ_HALO) + NY * (DIM == 3 ? lz + NQ_HALO : 0));
-    const T qx = sm.nqs[DIM][cc];
-    T nxv[3] = {0, 0, 0};
-#pragma unroll
-    for (int a = 0; a < DIM; ++a) nxv[a] = sm.nqs[a][cc];
+    const NQ<T> vx = sm.nq[cc];
+    const T qx = vx.q;
     const T tol = eta * (qx > eps_q ? qx : eps_q);
-    const int plane = lane8 - w;                  // dz (3D) or dy (2D)
-    const bool lane_ok = cell_ok && lane8 <= 2 * w;
+    const int plane = lane8 - WR;                  // dz (3D) or dy (2D)
+    const bool lane_ok = cell_ok && lane8 <= 2 * WR;
+    // first window cell of this lane: (dx, dy) = (-WR, -WR) in plane dz (3D), (-WR, dy) (2D)
+    const int row0 = lane_ok ? cc - WR + (DIM == 3 ? NX * (-WR + NY * plane) : NX * plane) : cc;
+    const int p2 = plane * plane;
+    auto accept = [&](const NQ<T>& v, T& dot) -> bool {
+      dot = vx.n0 * v.n0;
+      dot += vx.n1 * v.n1;
+      if (DIM == 3) dot += vx.n2 * v.n2;
+      return v.q >= q_th && m_abs(v.q - qx) <= tol && dot <= cos_opp;
+    };
     // pass 0
     int bd2 = 1 << 30;
     T bdot = (T)0;
     if (lane_ok) {
-      const int dz0 = DIM == 3 ? plane : 0, ylo = DIM == 3 ? -w : plane, yhi = DIM == 3 ? w : plane;
-      for (int dy = ylo; dy <= yhi; ++dy)
-        for (int dx = -w; dx <= w; ++dx) {
-          if ((dx | dy | dz0) == 0) continue;
-          const int cy_ = cc + dx + NX * (dy + NY * dz0);
-          const T qy = sm.nqs[DIM][cy_];
-          if (!(qy >= q_th)) continue;
-          if (!(m_abs(qy - qx) <= tol)) continue;
-          T dot = nxv[0] * sm.nqs[0][cy_];
-          dot += nxv[1] * sm.nqs[1][cy_];
-          if (DIM == 3) dot += nxv[2] * sm.nqs[2][cy_];
-          if (!(dot <= cos_opp)) continue;
-          const int d2 = dx * dx + dy * dy + dz0 * dz0;
-          if (d2 < bd2 || (d2 == bd2 && dot < bdot)) {
-            bd2 = d2;
-            bdot = dot;
-          }
+#pragma unroll 1
+      for (int r = 0; r < ROWS; ++r) {
+        // the row's cells are read first, then tested without branches
+        NQ<T> v[2 * WR + 1];
+#pragma unroll
+        for (int i = 0; i < 2 * WR + 1; ++i) v[i] = sm.nq[row0 + i + NX * r];
+        const int dyr = DIM == 3 ? r - WR : 0;
+#pragma unroll
+        for (int i = 0; i < 2 * WR + 1; ++i) {
+          const int dx = i - WR;
+          T dot;
+          const bool ok = accept(v[i], dot);
+          const int d2 = dx * dx + dyr * dyr + p2;
+          const bool self = dx == 0 && dyr == 0 && plane == 0;
+          const bool better = ok && !self && (d2 < bd2 || (d2 == bd2 && dot < bdot));
+          bd2 = better ? d2 : bd2;
+          bdot = better ? dot : bdot;
         }
+      }
     }
     group_min(bd2, bdot);
     const bool found = bd2 < (1 << 30);
     // pass 1: first candidate in scan order at distance bd2 within tie_eps of bdot
     int key = 1 << 30;
     if (lane_ok && found) {
-      const int dz0 = DIM == 3 ? plane : 0, ylo = DIM == 3 ? -w : plane, yhi = DIM == 3 ? w : plane;
-      bool done = false;
-      for (int dy = ylo; dy <= yhi && !done; ++dy)
-        for (int dx = -w; dx <= w; ++dx) {
-          const int d2 = dx * dx + dy * dy + dz0 * dz0;
+#pragma unroll 1
+      for (int r = ROWS - 1; r >= 0; --r)
+#pragma unroll
+        for (int i = 2 * WR; i >= 0; --i) {
+          const int dx = i - WR, dyr = DIM == 3 ? r - WR : 0;
+          const int d2 = dx * dx + dyr * dyr + p2;
           if (d2 != bd2) continue;
-          const int cy_ = cc + dx + NX * (dy + NY * dz0);
-          const T qy = sm.nqs[DIM][cy_];
-          if (!(qy >= q_th)) continue;
-          if (!(m_abs(qy - qx) <= tol)) continue;
-          T dot = nxv[0] * sm.nqs[0][cy_];
-          dot += nxv[1] * sm.nqs[1][cy_];
-          if (DIM == 3) dot += nxv[2] * sm.nqs[2][cy_];
-          if (!(dot <= cos_opp)) continue;
-          if (dot <= bdot + tie) {
-            // scan-order key: plane index, then row, then column
+          const NQ<T> v = sm.nq[row0 + i + NX * r];
+          T dot;
+          if (accept(v, dot) && dot <= bdot + tie) {
+            const int dy = DIM == 3 ? dyr : plane;
+            // scan-order key: plane index, then row, then column (scanning
+            // backwards, the last match is the first in scan order)
             key = ((lane8 * 16) + (dy + 8)) * 16 + (dx + 8);
-            done = true;
-            break;
           }
         }
     }
@@ -489,14 +556,15 @@ __device__ __forceinline__ void nci_tile(NciShared<DIM, T>& sm, unsigned t, cons
       T Jv[3] = {0, 0, 0};
       int packed = 0;
       if (found && key < (1 << 30)) {
-        const int kdx = (key & 15) - 8, kdy = ((key >> 4) & 15) - 8, kpl = (key >> 8) - w;
+        const int kdx = (key & 15) - 8, kdy = ((key >> 4) & 15) - 8, kpl = (key >> 8) - WR;
         const int bdx = kdx, bdy = DIM == 3 ? kdy : kpl, bdz = DIM == 3 ? kpl : 0;
-        const int cy_ = cc + bdx + NX * (bdy + NY * bdz);
-        const T qy = sm.nqs[DIM][cy_];
-        T dot = nxv[0] * sm.nqs[0][cy_];
-        dot += nxv[1] * sm.nqs[1][cy_];
-        if (DIM == 3) dot += nxv[2] * sm.nqs[2][cy_];
-        T qcl = (T)0.5 * (qx + qy);
+        const NQ<T> vy = sm.nq[cc + bdx + NX * (bdy + NY * bdz)];
+        const T nyv[3] = {vy.n0, vy.n1, vy.n2};
+        const T nxv[3] = {vx.n0, vx.n1, vx.n2};
+        T dot = nxv[0] * nyv[0];
+        dot += nxv[1] * nyv[1];
+        if (DIM == 3) dot += nxv[2] * nyv[2];
+        T qcl = (T)0.5 * (qx + vy.q);
         if (qcl < eps_q) qcl = eps_q;
         if (qcl > (T)0.25 - eps_q) qcl = (T)0.25 - eps_q;
         const T ff = -dot > (T)0 ? -dot : (T)0;
@@ -507,7 +575,7 @@ __device__ __forceinline__ void nci_tile(NciShared<DIM, T>& sm, unsigned t, cons
           T nt[3] = {0, 0, 0}, nn = 0;
 #pragma unroll
           for (int a = 0; a < DIM; ++a) {
-            nt[a] = nxv[a] - sm.nqs[a][cy_];
+            nt[a] = nxv[a] - nyv[a];
             nn += nt[a] * nt[a];
           }
           nn = m_sqrt(nn);
@@ -541,8 +609,8 @@ __device__ __forceinline__ void nci_tile(NciShared<DIM, T>& sm, unsigned t, cons
         my_active += 1u;
       }
 #pragma unroll
-      for (int a = 0; a < DIM; ++a) sm.gJ[gi][a] = Jv[a];
-      sm.gpart[gi] = packed;
+      for (int a = 0; a < DIM; ++a) sm.out.gJ[gi][a] = Jv[a];
+      sm.out.gpart[gi] = packed;
     }
   }
   __syncthreads();
@@ -554,10 +622,10 @@ __device__ __forceinline__ void nci_tile(NciShared<DIM, T>& sm, unsigned t, cons
     const int idx = gx + geo.nx * (gy + geo.ny * gz);
     const int sl = sm.gslot[e];
 #pragma unroll
-    for (int a = 0; a < DIM; ++a) J[a * geo.S + idx] = sl >= 0 ? sm.gJ[sl][a] : (T)0;
+    for (int a = 0; a < DIM; ++a) J[a * geo.S + idx] = sl >= 0 ? sm.out.gJ[sl][a] : (T)0;
     if constexpr (DEBUG) {
       const long long N = (long long)geo.nx * geo.ny * geo.nz;
-      const int pk = sl >= 0 ? sm.gpart[sl] : 0;
+      const int pk = sl >= 0 ? sm.out.gpart[sl] : 0;
       chi_out[idx] = pk != 0;
       part_out[idx] = pk ? ((pk - 1) & 31) - 8 : 0;
       part_out[N + idx] = pk ? (((pk - 1) >> 5) & 31) - 8 : 0;
@@ -565,6 +633,17 @@ __device__ __forceinline__ void nci_tile(NciShared<DIM, T>& sm, unsigned t, cons
     }
   }
   __syncthreads();
+}
+
+// The tile routine with the window radius as a compile-time constant.
+template <int DIM, typename T, bool DEBUG>
+__device__ __forceinline__ void nci_tile_w(NciShared<DIM, T>& sm, unsigned t, const T* __restrict__ phi,
+                                           T* __restrict__ J, int* __restrict__ chi_out,
+                                           int* __restrict__ part_out, const Geo& geo, const NciP& np,
+                                           unsigned& my_active) {
+  if (np.w == 3) nci_tile<DIM, T, DEBUG, 3>(sm, t, phi, J, chi_out, part_out, geo, np, my_active);
+  else if (np.w == 2) nci_tile<DIM, T, DEBUG, 2>(sm, t, phi, J, chi_out, part_out, geo, np, my_active);
+  else nci_tile<DIM, T, DEBUG, 1>(sm, t, phi, J, chi_out, part_out, geo, np, my_active);
 }
 
 template <int DIM, typename T, bool DEBUG>
@@ -581,7 +660,7 @@ __global__ __launch_bounds__(NT_NCI) void k_nci(const T* __restrict__ phi, T* __
   const unsigned ntiles = *cnt;
   unsigned my_active = 0;
   for (unsigned k = blockIdx.x; k < ntiles; k += gridDim.x)
-    nci_tile<DIM, T, DEBUG>(sm, list[k], phi, J, chi_out, part_out, geo, np, my_active);
+    nci_tile_w<DIM, T, DEBUG>(sm, list[k], phi, J, chi_out, part_out, geo, np, my_active);
   my_active = wave_sum(my_active);
   if ((threadIdx.x & 63) == 0 && my_active) atomicAdd(nci_count, my_active);
 }
@@ -1153,7 +1232,7 @@ __global__ __launch_bounds__(NT_NCI) void k_nci_multi(const Job<T, FS, GS>* __re
     const unsigned ntiles = jb.cnt[par];
     unsigned act = 0;
     for (unsigned k = blockIdx.x; k < ntiles; k += gridDim.x)
-      nci_tile<DIM, T, false>(sm, jb.list[par][k], jb.phi, jb.J, nullptr, nullptr, jb.geo, jb.np, act);
+      nci_tile_w<DIM, T, false>(sm, jb.list[par][k], jb.phi, jb.J, nullptr, nullptr, jb.geo, jb.np, act);
     act = wave_sum(act);
     if ((threadIdx.x & 63) == 0 && act) atomicAdd(jb.cnt + 2, act);
   }

@@ -53,11 +53,11 @@ class JobSpec:
 
 
 def make_jobs(count: int = 64, rate: float = 4.0, steps: int = 5000, seed: int = 4,
-              sizes=(64, 96, 128, 160, 192), precision: str = "fp32") -> List[JobSpec]:
+              sizes=(64, 96, 128, 160, 192), precision: str = "fp32", bubbles=(10, 50)) -> List[JobSpec]:
     """Seeded job stream: Poisson arrivals (exponential gaps of mean 1/rate),
     kind collision or swarm with equal odds, box edge uniform over `sizes`,
     collision relative speed U[0.02, 0.08] and impact parameter U[0, 0.6] R,
-    swarm bubble count uniform over 10..50."""
+    swarm bubble count uniform over bubbles[0]..bubbles[1]."""
     rng = np.random.Generator(np.random.PCG64(seed))
     t = 0.0
     jobs = []
@@ -71,7 +71,7 @@ def make_jobs(count: int = 64, rate: float = 4.0, steps: int = 5000, seed: int =
             spec.speed = float(rng.uniform(0.02, 0.08))
             spec.impact = float(rng.uniform(0.0, 0.6))
         else:
-            spec.bubbles = int(rng.integers(10, 51))
+            spec.bubbles = int(rng.integers(bubbles[0], bubbles[1] + 1))
         jobs.append(spec)
     return jobs
 
@@ -96,7 +96,8 @@ def job_state(spec: JobSpec) -> W.InitialState:
         r = spec.n / 8.0
         return W.droplet_pair(p, radius=r, separation=2.5 * r, speed=spec.speed / 2.0,
                               offset=spec.impact * r)
-    return W.bubble_swarm(p, spec.bubbles, max(5.0, spec.n / 16.0), spec.n / 10.0, 3.0, spec.seed)
+    rmin = max(5.0, spec.n / 16.0)
+    return W.bubble_swarm(p, spec.bubbles, rmin, max(rmin, spec.n / 10.0), 3.0, spec.seed)
 
 
 def job_bytes(spec: JobSpec) -> int:

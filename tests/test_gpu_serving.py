@@ -121,7 +121,7 @@ def test_serving_loop_small_stream():
     """A small served stream under a tight HBM budget: every job completes, the
     admitted bytes never exceed the budget, and each job's final state equals
     the state of the same job run alone."""
-    jobs = S.make_jobs(count=7, rate=40.0, steps=40, seed=4, sizes=(32, 48, 64))
+    jobs = S.make_jobs(count=7, rate=40.0, steps=40, seed=4, sizes=(32, 48, 64), bubbles=(2, 4))
     sizes = sorted((S.job_bytes(j) for j in jobs), reverse=True)
     budget = sizes[0] + sizes[1]
     announce(f"serving {len(jobs)} jobs, budget {budget} bytes")
