@@ -134,6 +134,8 @@ __device__ __forceinline__ double m_acosh(double a) { return acosh(a); }
 __device__ __forceinline__ float m_pow(float a, float b) { return powf(a, b); }
 __device__ __forceinline__ double m_pow(double a, double b) { return pow(a, b); }
 __device__ __forceinline__ float m_abs(float a) { return fabsf(a); }
+__device__ __forceinline__ float m_max(float a, float b) { return a > b ? a : b; }
+__device__ __forceinline__ double m_max(double a, double b) { return a > b ? a : b; }
 __device__ __forceinline__ double m_abs(double a) { return fabs(a); }
 
 // Periodic neighbours of a cell: index of x + (dx, dy, dz), |d| <= 1.
@@ -342,10 +344,8 @@ struct NciShared {
   NQ<T> nq[NNQ];
   short glist[TC];   // gated tile cells
   short gslot[TC];   // tile cell -> index in glist, or -1
-  T red[NT_NCI / 64][3];
-  T mhat[3];
+  T box[8][2][3];    // per sub-tile: smallest and largest normal components
   int ng;
-  int skip;
 };
 
 // Clears the tile flags of the other AA parity (set by the previous step) so
@@ -390,87 +390,113 @@ __device__ __forceinline__ void nci_tile(NciShared<DIM, T>& sm, unsigned t, cons
   const int tz = (int)(t / ((unsigned)geo.ntx * (unsigned)geo.nty));
   const int ox = tx * TX, oy = ty * TY, oz = tz * TZ;
   if (threadIdx.x == 0) sm.ng = 0;
-  // (1) phi tile with halo
-  for (int e = threadIdx.x; e < NPH; e += NT_NCI) {
-    const int ex = e % PX, ey = (e / PX) % PY, ez = e / (PX * PY);
-    const int gx = wrap_near(ox + ex - PHI_HALO, geo.nx), gy = wrap_near(oy + ey - PHI_HALO, geo.ny);
-    const int gz = DIM == 3 ? wrap_near(oz + ez - PHI_HALO, geo.nz) : 0;
-    sm.phs[e] = phi[gx + geo.nx * (gy + geo.ny * gz)];
+  // (1) phi tile with halo: lanes along x (one row of PX cells per PX lanes)
+  {
+    constexpr int RPI = NT_NCI / PX;                 // rows per pass
+    constexpr int NROW = NPH / PX;
+    const int ex = (int)threadIdx.x % PX, rr = (int)threadIdx.x / PX;
+    const int gx = wrap_near(ox + ex - PHI_HALO, geo.nx);
+    if (rr < RPI)
+      for (int r = rr; r < NROW; r += RPI) {
+        const int ey = r % PY, ez = r / PY;
+        const int gy = wrap_near(oy + ey - PHI_HALO, geo.ny);
+        const int gz = DIM == 3 ? wrap_near(oz + ez - PHI_HALO, geo.nz) : 0;
+        sm.phs[ex + PX * r] = phi[gx + geo.nx * (gy + geo.ny * gz)];
+      }
   }
   __syncthreads();
   // (2) indicator everywhere on tile + 3, normal where the indicator passes the gate
-  T msum[3] = {0, 0, 0};
-  for (int e = threadIdx.x; e < NNQ; e += NT_NCI) {
-    const int ex = e % NX, ey = (e / NX) % NY, ez = e / (NX * NY);
-    const int c = (ex + 1) + PX * ((ey + 1) + PY * (DIM == 3 ? ez + 1 : 0));
-    const T ph = sm.phs[c];
-    const T pc = ph < (T)0 ? (T)0 : (ph > (T)1 ? (T)1 : ph);
-    NQ<T> v{(T)0, (T)0, (T)0, pc * ((T)1 - pc)};
-    if (v.q >= q_th) {
-      T gr[3], lap;
-      grad_lap<DIM, T>([&](int i) { return sm.phs[c + L::cx[i] + PX * (L::cy[i] + PY * L::cz[i])]; },
-                       gr, lap);
-      T mag = gr[0] * gr[0] + gr[1] * gr[1];
-      if (DIM == 3) mag += gr[2] * gr[2];
-      mag = m_sqrt(mag);
-      const T den = mag + eps_n;
-      v.n0 = gr[0] / den;
-      v.n1 = gr[1] / den;
-      if (DIM == 3) v.n2 = gr[2] / den;
-      msum[0] += v.n0;
-      msum[1] += v.n1;
-      msum[2] += v.n2;
-    }
-    sm.nq[e] = v;
-  }
-  // (2b) can two normals of the region face each other?  With m the mean
-  // gated normal and c the smallest n.m/|m| over the gated cells, any two of
-  // them are at most 2 acos(c) apart, so n(x).n(y) >= 2c^2 - 1 (c >= 0).  When
-  // that bound exceeds cos_opp no cell of the tile can have a partner and the
-  // search is skipped (the tile's J is zero); a margin of 1e-3 covers rounding.
   {
-    const int wv = threadIdx.x >> 6;
+    constexpr int RPI = NT_NCI / NX;
+    constexpr int NROW = NNQ / NX;
+    const int ex = (int)threadIdx.x % NX, rr = (int)threadIdx.x / NX;
+    if (rr < RPI)
+      for (int r = rr; r < NROW; r += RPI) {
+        const int ey = r % NY, ez = r / NY;
+        const int c = (ex + 1) + PX * ((ey + 1) + PY * (DIM == 3 ? ez + 1 : 0));
+        const T ph = sm.phs[c];
+        const T pc = ph < (T)0 ? (T)0 : (ph > (T)1 ? (T)1 : ph);
+        NQ<T> v{(T)0, (T)0, (T)0, pc * ((T)1 - pc)};
+        if (v.q >= q_th) {
+          T gr[3], lap;
+          grad_lap<DIM, T>([&](int i) { return sm.phs[c + L::cx[i] + PX * (L::cy[i] + PY * L::cz[i])]; },
+                           gr, lap);
+          T mag = gr[0] * gr[0] + gr[1] * gr[1];
+          if (DIM == 3) mag += gr[2] * gr[2];
+          const T inv = (T)1 / (m_sqrt(mag) + eps_n);
+          v.n0 = gr[0] * inv;
+          v.n1 = gr[1] * inv;
+          if (DIM == 3) v.n2 = gr[2] * inv;
+        }
+        sm.nq[ex + NX * r] = v;
+      }
+  }
+  __syncthreads();
+  // (2b) per sub-tile (the tile halved along each axis) the range [lo, hi] of
+  // each normal component over the gated cells of the region that the windows
+  // of its cells cover.  One wave per sub-tile, lanes along x.
+  constexpr int SX = TX / 2, SY = TY / 2, SZ = DIM == 3 ? TZ / 2 : 1;
+  {
+    constexpr int RX = SX + 2 * NQ_HALO, RY = SY + 2 * NQ_HALO, RZ = DIM == 3 ? SZ + 2 * NQ_HALO : 1;
+    constexpr int NSUB = DIM == 3 ? 8 : 4;
+    constexpr int RPI = 64 / RX;
+    static_assert(NSUB <= NT_NCI / 64, "one wave per sub-tile");
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (wv < NSUB) {
+      const int bx = (wv & 1) * SX, by = ((wv >> 1) & 1) * SY, bz = DIM == 3 ? (wv >> 2) * SZ : 0;
+      const int rx = lane % RX, rr = lane / RX;
+      T lo[3] = {(T)1, (T)1, (T)1}, hi[3] = {(T)-1, (T)-1, (T)-1};
+      if (rr < RPI)
+        for (int r = rr; r < RY * RZ; r += RPI) {
+          const int ry = r % RY, rz = r / RY;
+          const NQ<T> v = sm.nq[(bx + rx) + NX * ((by + ry) + NY * (bz + rz))];
+          if (v.q >= q_th) {
+            const T n[3] = {v.n0, v.n1, v.n2};
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      const T v = wave_sum(msum[a]);
-      if ((threadIdx.x & 63) == 0) sm.red[wv][a] = v;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      T m[3] = {0, 0, 0};
-      for (int k = 0; k < NT_NCI / 64; ++k)
-        for (int a = 0; a < 3; ++a) m[a] += sm.red[k][a];
-      const T mm = m_sqrt(m[0] * m[0] + m[1] * m[1] + m[2] * m[2]);
-      for (int a = 0; a < 3; ++a) sm.mhat[a] = mm > (T)1e-6 ? m[a] / mm : (T)0;
-    }
-    __syncthreads();
-    const T mh[3] = {sm.mhat[0], sm.mhat[1], sm.mhat[2]};
-    T cmin = (T)1;
-    for (int e = threadIdx.x; e < NNQ; e += NT_NCI) {
-      const NQ<T> v = sm.nq[e];
-      if (v.q >= q_th) {
-        const T d = v.n0 * mh[0] + v.n1 * mh[1] + v.n2 * mh[2];
-        cmin = d < cmin ? d : cmin;
+            for (int a = 0; a < 3; ++a) {
+              lo[a] = n[a] < lo[a] ? n[a] : lo[a];
+              hi[a] = n[a] > hi[a] ? n[a] : hi[a];
+            }
+          }
+        }
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        lo[a] = wave_min(lo[a]);
+        hi[a] = wave_max(hi[a]);
+      }
+      if (lane == 0) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          sm.box[wv][0][a] = lo[a];
+          sm.box[wv][1][a] = hi[a];
+        }
       }
     }
-    cmin = wave_min(cmin);
-    if ((threadIdx.x & 63) == 0) sm.red[wv][0] = cmin;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      T c = (T)1;
-      for (int k = 0; k < NT_NCI / 64; ++k) c = sm.red[k][0] < c ? sm.red[k][0] : c;
-      sm.skip = c >= (T)0 && (T)2 * c * c - (T)1 > cos_opp + (T)1e-3;
-    }
     __syncthreads();
   }
-  const bool skip = sm.skip != 0;
-  // (3) list the gated cells of the tile
+  // (3) list the gated cells of the tile that may have a partner.  Every
+  // candidate y of cell x in sub-tile s has n(y) in the box of s, so
+  // n(x).n(y) >= sum_a min(n_a(x) lo_a, n_a(x) hi_a); when that bound exceeds
+  // cos_opp (margin 1e-3 for rounding) x has no partner and its flux is zero.
   for (int e = threadIdx.x; e < TC; e += NT_NCI) {
     const int lx = e % TX, ly = (e / TX) % TY, lz = e / (TX * TY);
     const bool inside = ox + lx < geo.nx && oy + ly < geo.ny && oz + lz < geo.nz;
     const int cc = (lx + NQ_HALO) + NX * ((ly + NQ_HALO) + NY * (DIM == 3 ? lz + NQ_HALO : 0));
     short slot = -1;
-    if (!skip && inside && sm.nq[cc].q >= q_th) {
+    const NQ<T> v = sm.nq[cc];
+    bool open = inside && v.q >= q_th;
+    if (open) {
+      const int sub = (lx >= SX ? 1 : 0) + (ly >= SY ? 2 : 0) + (DIM == 3 && lz >= SZ ? 4 : 0);
+      const T n[3] = {v.n0, v.n1, v.n2};
+      T bound = (T)0;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const T p = n[a] * sm.box[sub][0][a], q = n[a] * sm.box[sub][1][a];
+        bound += p < q ? p : q;
+      }
+      open = !(bound > cos_opp + (T)1e-3);
+    }
+    if (open) {
       slot = (short)atomicAdd(&sm.ng, 1);
       sm.glist[slot] = (short)e;
     }
