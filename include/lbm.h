@@ -96,6 +96,17 @@ typedef struct {
                                 the periodic lattice, by union-find on the device       */
   long nci_active;           /* number of cells with chi_nc = 1                             */
   int finite;                /* 1 if every p*, u and phi is finite                          */
+  /* Sec. 3.3 (self-tuning of the repulsion): sums over the film region (cells
+   * with a partner, F_rep != 0) of |F_rep . n| and |F_cap . n| (numerator and
+   * denominator of Eq. RnAbs) and of |F_rep|, with F_rep = rho J, F_cap =
+   * mu_phi grad phi, n = grad phi / (|grad phi| + eps_n); the film volume in
+   * cells; the largest |F_rep|.  R_n = film_frep_n / film_fcap_n and
+   * <|F_rep|>_film = film_frep / film_cells.  Accumulated in FP64.             */
+  double film_cells;
+  double film_frep_n;
+  double film_fcap_n;
+  double film_frep;
+  double max_frep;
 } lbm_diag;
 
 typedef struct lbm_ctx lbm_ctx;

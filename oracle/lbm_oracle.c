@@ -825,6 +825,24 @@ int oracle_diagnostics(oracle_state* s, oracle_diag* out) {
     if (sp > out->max_speed) out->max_speed = sp;
     out->nci_active += s->chi[idx];
     if (!isfinite(s->phi[idx]) || !isfinite(sp) || !isfinite(s->pstar[idx])) out->finite = 0;
+    /* film diagnostics of Sec. 3.3 (Eq. RnAbs): F_rep = rho J (Eq. Frep_impl),
+     * F_cap = mu grad phi (Eq. Fcap), n = grad phi / (|grad phi| + eps_n) */
+    double frep2 = 0.0, frep_n = 0.0, fcap_n = 0.0;
+    for (int a = 0; a < D; ++a) {
+      const double fr = rho * s->J[a * N + idx];
+      const double fc = s->mu[idx] * s->grad[a * N + idx];
+      const double na = s->nrm[a * N + idx];
+      frep2 += fr * fr;
+      frep_n += fr * na;
+      fcap_n += fc * na;
+    }
+    const double frep = sqrt(frep2);
+    if (frep > out->max_frep) out->max_frep = frep;
+    if (s->chi[idx]) {
+      out->film_frep_n += fabs(frep_n);
+      out->film_fcap_n += fabs(fcap_n);
+      out->film_frep += frep;
+    }
   }
   out->n_droplets = oracle_count_components(D, (int)s->nx, (int)s->ny, (int)s->nz, s->phi, s->dispersed);
   return 0;

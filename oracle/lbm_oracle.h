@@ -42,6 +42,11 @@ typedef struct {
   double mass_phi, sum_pstar, momentum[3], kinetic_energy, max_speed;
   long n_droplets, nci_active;
   int finite;
+  /* Sec. 3.3 (self-tuning of the repulsion), over the film region chi = 1:
+   * sums of |F_rep . n|, |F_cap . n| (Eq. RnAbs, numerator and denominator)
+   * and |F_rep| with F_rep = rho J, F_cap = mu_phi grad phi, n the unit normal;
+   * max_frep = max |F_rep| over all cells. */
+  double film_frep_n, film_fcap_n, film_frep, max_frep;
 } oracle_diag;
 
 typedef struct oracle_state oracle_state;

@@ -35,7 +35,13 @@ constexpr int NT = BX * BY;
 constexpr int NT_NCI = 512;   // near-contact kernel: two blocks of 512 per CU fit its LDS
 constexpr int PHI_HALO = 4;   // window radius 3 + 1 for the normals
 constexpr int NQ_HALO = 3;    // window radius
-constexpr int NPART = 8;      // doubles per block in the reduction scratch
+constexpr int NPART = 16;     // doubles per block in the reduction scratch
+
+// Reduction slots of the collide pass (k_diag uses 0 phi, 1 droplet roots,
+// 6 non-finite): 0 p*, 1-3 rho u, 4 kinetic energy, 5 max |u|, 6 non-finite,
+// 7 near-contact cells, 8 film cells, 9 |F_rep.n|, 10 |F_cap.n|, 11 |F_rep|
+// (sums over the film), 12 max |F_rep|.  Slots 5 and 12 reduce by maximum.
+__host__ __device__ constexpr bool max_slot(int k) { return k == 5 || k == 12; }
 
 struct Geo {
   int nx, ny, nz;
@@ -697,12 +703,13 @@ __global__ __launch_bounds__(NT_NCI) void k_nci(const T* __restrict__ phi, T* __
 
 enum { MODE_STEP = 0, MODE_STEP_DIAG = 1, MODE_DRY = 2 };
 
-// Block reduction of the NPART per-thread values (sums, except slot 5 = max).
+// Block reduction of the NPART per-thread values (sums, or maxima in the
+// max_slot slots).
 __device__ __forceinline__ void block_partials(double v[NPART], double* __restrict__ out) {
   __shared__ double red[NT / 64][NPART];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
-  for (int k = 0; k < NPART; ++k) v[k] = (k == 5) ? wave_max(v[k]) : wave_sum(v[k]);
+  for (int k = 0; k < NPART; ++k) v[k] = max_slot(k) ? wave_max(v[k]) : wave_sum(v[k]);
   if (lane == 0)
 #pragma unroll
     for (int k = 0; k < NPART; ++k) red[wv][k] = v[k];
@@ -710,7 +717,7 @@ __device__ __forceinline__ void block_partials(double v[NPART], double* __restri
   if (threadIdx.x < NPART) {
     const int k = threadIdx.x;
     double a = red[0][k];
-    for (int j = 1; j < NT / 64; ++j) a = (k == 5) ? (red[j][k] > a ? red[j][k] : a) : a + red[j][k];
+    for (int j = 1; j < NT / 64; ++j) a = max_slot(k) ? (red[j][k] > a ? red[j][k] : a) : a + red[j][k];
     out[blockIdx.x * NPART + k] = a;
   }
 }
@@ -941,6 +948,26 @@ __device__ __forceinline__ void collide_cell(const Planes<FS, GS>& pl, const T* 
     const bool fin = isfinite((double)ps) && isfinite(sp2);
     acc[6] = fin ? 0.0 : 1.0;
     if (!fin) acc[5] = 0.0;
+    // film region of the near-contact force (J != 0 exactly where a partner was
+    // found): Sec. 3.3 sums of |F_rep.n|, |F_cap.n|, |F_rep| (Eq. RnAbs) with
+    // F_rep = rho J, F_cap = mu grad phi and n the unit normal of the step
+    if (Jv[0] != (T)0 || Jv[1] != (T)0 || Jv[2] != (T)0) {
+      double fr2 = 0.0, frn = 0.0, fcn = 0.0;
+#pragma unroll
+      for (int a = 0; a < DIM; ++a) {
+        const double fr = dr * (double)Jv[a];
+        const double fc = (double)mu * (double)gr[a];
+        const double na = (double)(gr[a] * inv_g);
+        fr2 += fr * fr;
+        frn += fr * na;
+        fcn += fc * na;
+      }
+      acc[8] = 1.0;
+      acc[9] = fabs(frn);
+      acc[10] = fabs(fcn);
+      acc[11] = sqrt(fr2);
+      acc[12] = acc[11];
+    }
   }
 }
 
@@ -955,7 +982,7 @@ __global__ __launch_bounds__(NT) void k_collide(Planes<FS, GS> pl, const T* __re
   int x, y, z;
   block_cell(swizzled_block(), geo, x, y, z);
   const bool valid = x < geo.nx && y < geo.ny;
-  double acc[NPART] = {0, 0, 0, 0, 0, 0, 0, 0};
+  double acc[NPART] = {};
   if (MODE == MODE_STEP && !valid) return;
   if (valid) collide_cell<DIM, PAR, MODE, T, FS, GS, OFF32>(pl, phi, J, flags, geo, pp, nci_on, macro, x, y, z, acc);
   if constexpr (MODE != MODE_STEP) block_partials(acc, partials);
@@ -1045,7 +1072,7 @@ __global__ __launch_bounds__(NT) void k_diag(const T* __restrict__ phi, Geo geo,
                                              double* __restrict__ partials) {
   int x, y, z;
   block_cell(swizzled_block(), geo, x, y, z);
-  double acc[NPART] = {0, 0, 0, 0, 0, 0, 0, 0};
+  double acc[NPART] = {};
   if (x < geo.nx && y < geo.ny) {
     const unsigned idx = (unsigned)Nbr(x, y, z, geo)(0, 0, 0);
     const T p0 = phi[idx];
@@ -1062,15 +1089,15 @@ __global__ __launch_bounds__(NT) void k_reduce_stage(const double* __restrict__ 
                                                      double* __restrict__ out) {
   __shared__ double red[NT][NPART];
   const int lo = blockIdx.x * chunk, hi = min(n, lo + chunk);
-  double v[NPART] = {0, 0, 0, 0, 0, 0, 0, 0};
+  double v[NPART] = {};
   for (int b = lo + (int)threadIdx.x; b < hi; b += NT)
-    for (int k = 0; k < NPART; ++k) v[k] = (k == 5) ? fmax(v[k], p[b * NPART + k]) : v[k] + p[b * NPART + k];
+    for (int k = 0; k < NPART; ++k) v[k] = max_slot(k) ? fmax(v[k], p[b * NPART + k]) : v[k] + p[b * NPART + k];
   for (int k = 0; k < NPART; ++k) red[threadIdx.x][k] = v[k];
   __syncthreads();
   for (int s = NT / 2; s > 0; s >>= 1) {
     if ((int)threadIdx.x < s)
       for (int k = 0; k < NPART; ++k)
-        red[threadIdx.x][k] = (k == 5) ? fmax(red[threadIdx.x][k], red[threadIdx.x + s][k])
+        red[threadIdx.x][k] = max_slot(k) ? fmax(red[threadIdx.x][k], red[threadIdx.x + s][k])
                                        : red[threadIdx.x][k] + red[threadIdx.x + s][k];
     __syncthreads();
   }
@@ -1087,15 +1114,15 @@ __global__ __launch_bounds__(NT) void k_reduce(const double* __restrict__ pa, in
   for (int pass = 0; pass < 2; ++pass) {
     const double* p = pass ? pb : pa;
     const int n = pass ? nb_ : na;
-    double v[NPART] = {0, 0, 0, 0, 0, 0, 0, 0};
+    double v[NPART] = {};
     for (int b = threadIdx.x; b < n; b += NT)
-      for (int k = 0; k < NPART; ++k) v[k] = (k == 5) ? fmax(v[k], p[b * NPART + k]) : v[k] + p[b * NPART + k];
+      for (int k = 0; k < NPART; ++k) v[k] = max_slot(k) ? fmax(v[k], p[b * NPART + k]) : v[k] + p[b * NPART + k];
     for (int k = 0; k < NPART; ++k) red[threadIdx.x][k] = v[k];
     __syncthreads();
     for (int s = NT / 2; s > 0; s >>= 1) {
       if ((int)threadIdx.x < s)
         for (int k = 0; k < NPART; ++k)
-          red[threadIdx.x][k] = (k == 5) ? fmax(red[threadIdx.x][k], red[threadIdx.x + s][k])
+          red[threadIdx.x][k] = max_slot(k) ? fmax(red[threadIdx.x][k], red[threadIdx.x + s][k])
                                          : red[threadIdx.x][k] + red[threadIdx.x + s][k];
       __syncthreads();
     }

@@ -279,6 +279,11 @@ void fill_diag(const double* r, long step, lbm_diag* d) {
   d->mass_phi = r[NPART + 0];
   d->n_droplets = (long)std::llround(r[NPART + 1]);
   d->finite = (r[6] == 0.0 && r[NPART + 6] == 0.0 && std::isfinite(r[NPART + 0])) ? 1 : 0;
+  d->film_cells = r[8];
+  d->film_frep_n = r[9];
+  d->film_fcap_n = r[10];
+  d->film_frep = r[11];
+  d->max_frep = r[12];
 }
 
 template <int DIM, typename T, typename FS, typename GS>

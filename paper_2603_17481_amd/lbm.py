@@ -53,6 +53,8 @@ class lbm_diag(C.Structure):
         ("step", C.c_long), ("mass_phi", C.c_double), ("sum_pstar", C.c_double),
         ("momentum", C.c_double * 3), ("kinetic_energy", C.c_double), ("max_speed", C.c_double),
         ("n_droplets", C.c_long), ("nci_active", C.c_long), ("finite", C.c_int),
+        ("film_cells", C.c_double), ("film_frep_n", C.c_double), ("film_fcap_n", C.c_double),
+        ("film_frep", C.c_double), ("max_frep", C.c_double),
     ]
 
 
@@ -154,7 +156,8 @@ def _diag_dict(d: lbm_diag, dim: int) -> dict:
     return {"step": d.step, "mass_phi": d.mass_phi, "sum_pstar": d.sum_pstar,
             "momentum": list(d.momentum)[:dim], "kinetic_energy": d.kinetic_energy,
             "max_speed": d.max_speed, "n_droplets": d.n_droplets, "nci_active": d.nci_active,
-            "finite": bool(d.finite)}
+            "finite": bool(d.finite), "film_cells": d.film_cells, "film_frep_n": d.film_frep_n,
+            "film_fcap_n": d.film_fcap_n, "film_frep": d.film_frep, "max_frep": d.max_frep}
 
 
 class Lattice:

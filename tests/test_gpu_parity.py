@@ -159,6 +159,22 @@ def test_fp64_diagnostics_parity():
     assert dg["finite"] and do["finite"]
 
 
+@pytest.mark.parametrize("dim", [2, 3])
+def test_fp64_film_diagnostics_parity(dim):
+    """Sec. 3.3 film diagnostics (Eq. RnAbs sums, film volume, peak repulsion)
+    against the oracle, in FP64, on near-contact pairs after 100 steps."""
+    st = near_contact_pair(dim)
+    g, o = run_pair(st, 100)
+    dg, do = g.diagnostics(), o.diagnostics()
+    print(f"[gpu-case] film {dim}D gpu {[dg[k] for k in ('film_cells', 'film_frep_n', 'film_fcap_n', 'film_frep', 'max_frep')]}"
+          f" oracle {[do[k] for k in ('nci_active', 'film_frep_n', 'film_fcap_n', 'film_frep', 'max_frep')]}",
+          flush=True)
+    assert dg["film_cells"] == dg["nci_active"] == do["nci_active"] > 0
+    for k in ("film_frep_n", "film_fcap_n", "film_frep", "max_frep"):
+        assert do[k] > 0
+        assert abs(dg[k] - do[k]) <= 1e-12 * do[k], (k, dg[k], do[k])
+
+
 # ---------------------------------------------------------------------------
 # FP32
 # ---------------------------------------------------------------------------

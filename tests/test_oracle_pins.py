@@ -596,3 +596,76 @@ def test_storage_rounding_knob():
     f, _ = o.get_populations()
     bits = f.astype(np.float32).view(np.uint32)
     assert np.all((bits & 0xFFFF) == 0)
+
+
+# ---------------------------------------------------------------------------
+# Film diagnostics of the self-tuning study (Sec. 3.3, Eq. RnAbs)
+# ---------------------------------------------------------------------------
+
+def test_film_diagnostics_planar_film_and_isolated_droplet():
+    """A planar symmetric film carries a purely normal repulsion, so the film sum of
+    |F_rep.n| equals that of |F_rep| (n has length |grad phi|/(|grad phi|+eps_n));
+    the film volume is the number of cells with a partner and the largest |F_rep| is
+    that of the strongest film cell.  An isolated droplet has no film."""
+    N = 48
+    p = W.Params(dim=2, nx=N, ny=6, width=4.0, sigma=1e-3, a_rep=1e-3)
+    st = W.slab(p, N - 5.0, axis=0, center=(N - 1) / 2 - N / 2)
+    o = O.Oracle(p)
+    o.init_fields(st.phi)
+    d = o.diagnostics()
+    chi, _, J = o.nci()
+    F = np.sqrt(((J * o.rho()) ** 2).sum(axis=0))
+    assert d["nci_active"] == chi.sum() > 0
+    assert d["film_frep"] > 0 and d["film_fcap_n"] > 0
+    assert abs(d["film_frep_n"] - d["film_frep"]) <= 1e-9 * d["film_frep"]
+    assert d["max_frep"] == pytest.approx(F.max(), rel=1e-15)
+    p3 = W.Params(dim=3, nx=24, ny=24, nz=24, width=5.0, sigma=5e-3, a_rep=5e-3, density_ratio=10.0)
+    s3 = W.static_droplet(p3, 6.0)
+    o3 = O.Oracle(p3)
+    o3.init_fields(s3.phi)
+    d3 = o3.diagnostics()
+    assert d3["nci_active"] == 0
+    assert d3["film_frep_n"] == d3["film_fcap_n"] == d3["film_frep"] == d3["max_frep"] == 0.0
+
+
+def test_film_diagnostics_scale_with_amplitude():
+    """J is linear in A_rep (Eq. Jrep_impl) and the partner map does not depend on
+    it: on the same state, doubling A_rep doubles every film sum of F_rep and the
+    peak, and leaves the film volume and the capillary sum unchanged."""
+    p = W.Params(dim=2, nx=64, ny=48, width=4.0, sigma=1e-3, a_rep=1e-3)
+    st = W.droplet_pair(p, radius=12.0, separation=27.0, speed=0.03)
+    ds = []
+    for a in (1e-3, 2e-3):
+        o = O.Oracle(p.replace(a_rep=a))
+        o.init_fields(st.phi, st.u)
+        ds.append(o.diagnostics())
+    d1, d2 = ds
+    assert d1["nci_active"] == d2["nci_active"] > 0
+    for k in ("film_frep_n", "film_frep", "max_frep"):
+        assert d2[k] == pytest.approx(2.0 * d1[k], rel=1e-14)
+    assert d2["film_fcap_n"] == pytest.approx(d1["film_fcap_n"], rel=1e-15)
+
+
+def test_film_diagnostics_match_exported_fields():
+    """The film sums equal the same sums formed from the exported fields: film mask
+    chi = 1, F_rep = rho J, F_cap = mu_phi grad phi, n the unit normal (3D pair
+    after 30 steps, so that the flow and the capillary force are developed)."""
+    from tests.helpers import near_contact_pair
+    st = near_contact_pair(3)
+    o = O.Oracle(st.params)
+    o.init_fields(st.phi, st.u)
+    o.step(30)
+    d = o.diagnostics()
+    g, _, n, _, mu = o.gradients()
+    chi, _, J = o.nci()
+    Fr = J * o.rho()
+    Fc = mu * g
+    m = chi == 1
+    assert m.sum() > 0
+    frn = np.abs((Fr * n).sum(axis=0))[m].sum()
+    fcn = np.abs((Fc * n).sum(axis=0))[m].sum()
+    fr = np.sqrt((Fr ** 2).sum(axis=0))
+    assert d["film_frep_n"] == pytest.approx(frn, rel=1e-12)
+    assert d["film_fcap_n"] == pytest.approx(fcn, rel=1e-12)
+    assert d["film_frep"] == pytest.approx(fr[m].sum(), rel=1e-12)
+    assert d["max_frep"] == pytest.approx(fr.max(), rel=1e-14)
