@@ -10,8 +10,7 @@
 //              structure-of-arrays; reads J only in flagged tiles.
 //   k_diag     FP64 sums of phi and the droplet count (k_cc_init / k_cc_merge:
 //              union-find labels of the dispersed set).
-// Grids are 1-D with an XCD-aware block swizzle: consecutive tiles of the domain
-// land on the same XCD so that stencil re-reads hit its L2.
+// Grids are 1-D; the block-to-tile mapping is XCD-aware (slab_block).
 //
 // Floating-point contraction is off for all of this code: every kernel that
 // runs the per-cell update (single lattice, batch of lattices, with or without
@@ -46,8 +45,10 @@ __host__ __device__ constexpr bool max_slot(int k) { return k == 5 || k == 12; }
 struct Geo {
   int nx, ny, nz;
   int nbx, nby;          // blocks along x and y (BX x BY cells each)
-  long long S;           // plane stride of the structure-of-arrays fields
+  long long S;           // plane stride of the structure-of-arrays fields (phi, J)
   int ntx, nty, ntz;     // near-contact tiles along x, y, z
+  int rs;                // population chunks hold R = 2^rs rows ...
+  int qc;                // ... i.e. qc = R nx cells per population
 };
 
 struct Phys {
@@ -88,6 +89,9 @@ struct NciTile<3, double> {
 // small helpers
 // ---------------------------------------------------------------------------
 
+// XCD k (blocks b = k mod 8) takes the k-th eighth of the grid: the mapping of
+// the multi-lattice launches and of the kernels whose atomics (tile flags and
+// lists, component labels) should stay within one XCD's L2.
 __device__ __forceinline__ int swizzled_block() {
   const int b = blockIdx.x, n = gridDim.x;
   const int full = n & ~7;
@@ -163,6 +167,51 @@ struct Nbr {
   }
   __device__ __forceinline__ int operator()(int dx, int dy, int dz) const {
     return xs[dx + 1] + ys[dy + 1] + (int)zs[dz + 1];
+  }
+};
+
+// Population layout.  Within each z plane the rows are grouped in chunks of
+// R = 2^rs rows, and a chunk stores the Q population planes of its qc = R nx
+// cells one after the other.  Element (q; x, y, z) of an array of Q populations:
+//   z nx ny Q + (y >> rs) Q qc + q qc + (y mod R) nx + x.
+// A block covers cells of one z plane, so the z term is uniform over it and
+// goes into the (scalar) base pointer; the rest, below nx ny Q, is the lane's
+// offset.  The 26 streams of a block then fall into a few contiguous regions
+// of a z plane instead of 26 planes gigabytes apart.
+template <typename E>
+__device__ __forceinline__ E* pop_zplane(E* base, int z, const Geo& g, int Q) {
+  return base + (size_t)z * ((size_t)g.nx * g.ny * Q);
+}
+__device__ __forceinline__ unsigned pop_row(int y, const Geo& g, int Q) {
+  return (unsigned)(y >> g.rs) * (unsigned)(Q * g.qc) + (unsigned)(y & ((1 << g.rs) - 1)) * (unsigned)g.nx;
+}
+__device__ __forceinline__ size_t pop_elem(int q, int x, int y, int z, const Geo& g, int Q) {
+  return (size_t)z * ((size_t)g.nx * g.ny * Q) + pop_row(y, g, Q) + (unsigned)x + (unsigned)(q * g.qc);
+}
+
+// Periodic neighbourhood of a cell in the population layout of an array of Q
+// populations: x' and the row part of the offset for y' = y - 1, y, y + 1, and
+// the z plane bases for z - 1, z, z + 1.
+template <typename E>
+struct PopNbr {
+  unsigned xs[3], ys[3];
+  E* zp[3];
+  unsigned qc;
+  __device__ PopNbr(E* base, int x, int y, int z, const Geo& g, int Q) : qc((unsigned)g.qc) {
+    xs[0] = (unsigned)(x == 0 ? g.nx - 1 : x - 1);
+    xs[1] = (unsigned)x;
+    xs[2] = (unsigned)(x == g.nx - 1 ? 0 : x + 1);
+    ys[0] = pop_row(y == 0 ? g.ny - 1 : y - 1, g, Q);
+    ys[1] = pop_row(y, g, Q);
+    ys[2] = pop_row(y == g.ny - 1 ? 0 : y + 1, g, Q);
+    zp[0] = pop_zplane(base, z == 0 ? g.nz - 1 : z - 1, g, Q);
+    zp[1] = pop_zplane(base, z, g, Q);
+    zp[2] = pop_zplane(base, z == g.nz - 1 ? 0 : z + 1, g, Q);
+  }
+  // population q of the cell at offset (dx, dy, dz)
+  template <bool OFF32>
+  __device__ __forceinline__ E* at(int q, int dx, int dy, int dz) const {
+    return plane_at<OFF32>(zp[dz + 1], ys[dy + 1] + xs[dx + 1] + (unsigned)q * qc);
   }
 };
 
@@ -260,13 +309,13 @@ __device__ __forceinline__ void phi_cell(const GS* __restrict__ g, T* __restrict
   using TL = NciTile<DIM, T>;
   const int idx = x + geo.nx * (y + geo.ny * z);
   double acc = 0.0;
+  const PopNbr<const GS> pn(g, x, y, z, geo, P::Q);
   if constexpr (PAR == 0) {
 #pragma unroll
-    for (int i = 0; i < P::Q; ++i) acc += (double)g[i * geo.S + idx];
+    for (int i = 0; i < P::Q; ++i) acc += (double)*pn.template at<false>(i, 0, 0, 0);
   } else {
-    const Nbr nb(x, y, z, geo);
 #pragma unroll
-    for (int i = 0; i < P::Q; ++i) acc += (double)g[opp(i) * geo.S + nb(-P::cx[i], -P::cy[i], -P::cz[i])];
+    for (int i = 0; i < P::Q; ++i) acc += (double)*pn.template at<false>(opp(i), -P::cx[i], -P::cy[i], -P::cz[i]);
   }
   const T s = (T)acc;
   phi[idx] = s;
@@ -278,6 +327,23 @@ __device__ __forceinline__ void phi_cell(const GS* __restrict__ g, T* __restrict
       if (flags[tile] == 0u && atomicExch(&flags[tile], 1u) == 0u) list[atomicAdd(cnt, 1u)] = tile;
     }
   }
+}
+
+// Tile of block for the fused collide + stream.  The hardware deals blocks to
+// the 8 XCDs round-robin (block b to XCD b mod 8); here XCD k takes the slabs
+// k, k + 8, k + 16, ... of the domain in order, a slab being a z plane in 3D
+// and a row of blocks in 2D.  The XCDs thus stream through neighbouring slabs
+// together, which keeps the HBM traffic of the moment within a few planes
+// (2 % faster than giving each XCD one contiguous eighth); slabs beyond the
+// last multiple of 8 keep their own order.
+__device__ __forceinline__ int slab_block(const Geo& g) {
+  const int b = blockIdx.x;
+  const int per = g.nz > 1 ? g.nbx * g.nby : g.nbx;   // blocks per slab
+  const int nslab = g.nz > 1 ? g.nz : g.nby;
+  const int full = (nslab & ~7) * per;
+  if (b >= full) return b;
+  const int k = b & 7, i = b >> 3;
+  return (k + 8 * (i / per)) * per + i % per;
 }
 
 // Cell of thread: block t of a domain covers BX x BY cells of one z plane.
@@ -722,12 +788,11 @@ __device__ __forceinline__ void block_partials(double v[NPART], double* __restri
   }
 }
 
-// Base pointer of every population plane (kernel arguments, so they live in
-// scalar registers and each access is base + 32-bit lane offset).
+// Base pointers of the two population arrays (kernel arguments).
 template <typename FS, typename GS>
 struct Planes {
-  FS* f[19];
-  GS* g[9];
+  FS* f;   // hydrodynamic populations
+  GS* g;   // phase-field populations
 };
 
 // Mixture and forcing constants in the arithmetic type of the kernel.
@@ -782,12 +847,13 @@ __device__ __forceinline__ void collide_cell(const Planes<FS, GS>& pl, const T* 
   const T nu = (pp.mu_a + pp.mu_b * ph) * inv_rho;
   const T omega = m_rcp((T)0.5 + (T)3 * nu);
   // ---- hydrodynamic populations and their moments
+  const PopNbr<FS> pf(pl.f, x, y, z, geo, Q);
   T fi[Q];
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
-    const FS* fp = pl.f[PAR == 0 ? i : opp(i)];
-    const unsigned src = PAR == 0 ? idx : (unsigned)nb(-H::cx[i], -H::cy[i], -H::cz[i]);
-    fi[i] = Store<FS>::ld(plane_at<OFF32>(fp, src), pp.fref[i]);
+    const FS* src = PAR == 0 ? pf.template at<OFF32>(i, 0, 0, 0)
+                             : pf.template at<OFF32>(opp(i), -H::cx[i], -H::cy[i], -H::cz[i]);
+    fi[i] = Store<FS>::ld(src, pp.fref[i]);
   }
   T ps = fi[0], m[3] = {0, 0, 0}, M2[6] = {0, 0, 0, 0, 0, 0};  // xx yy zz xy xz yz
 #pragma unroll
@@ -869,7 +935,7 @@ __device__ __forceinline__ void collide_cell(const Planes<FS, GS>& pl, const T* 
     const T A1[3] = {u[0] + F[0] * inv2rho, u[1] + F[1] * inv2rho, u[2] + F[2] * inv2rho};
     const T base = ps - (T)1.5 * trB;
     const T k3 = (T)13.5 * om1, k3t = (T)4.5 * om1 * trA, k3u = (T)9 * om1;
-    Store<FS>::st(plane_at<OFF32>(pl.f[0], idx), wt<H, T>(0) * base, pp.fref[0]);
+    Store<FS>::st(pf.template at<OFF32>(0, 0, 0, 0), wt<H, T>(0) * base, pp.fref[0]);
 #pragma unroll
     for (int i = 1; i < Q; i += 2) {
       const int cx = H::cx[i], cy = H::cy[i], cz = H::cz[i];
@@ -883,14 +949,12 @@ __device__ __forceinline__ void collide_cell(const Planes<FS, GS>& pl, const T* 
       const T t3 = fmad(cu, fmad(k3, cAc, fmad((T)4.5, fmad(cu, cu, -uu), -k3t)), -(k3u * cAu));
       const T od = w * fmad((T)3, cA1, t3);
       const T fa = ev + od, fb = ev - od;   // directions i and opp(i)
-      FS* const pi = pl.f[i];
-      FS* const pj = pl.f[i + 1];
       if constexpr (PAR == 0) {
-        Store<FS>::st(plane_at<OFF32>(pj, idx), fa, pp.fref[i]);
-        Store<FS>::st(plane_at<OFF32>(pi, idx), fb, pp.fref[i]);
+        Store<FS>::st(pf.template at<OFF32>(i + 1, 0, 0, 0), fa, pp.fref[i]);
+        Store<FS>::st(pf.template at<OFF32>(i, 0, 0, 0), fb, pp.fref[i]);
       } else {
-        Store<FS>::st(plane_at<OFF32>(pi, (unsigned)nb(cx, cy, cz)), fa, pp.fref[i]);
-        Store<FS>::st(plane_at<OFF32>(pj, (unsigned)nb(-cx, -cy, -cz)), fb, pp.fref[i]);
+        Store<FS>::st(pf.template at<OFF32>(i, cx, cy, cz), fa, pp.fref[i]);
+        Store<FS>::st(pf.template at<OFF32>(i + 1, -cx, -cy, -cz), fb, pp.fref[i]);
       }
     }
     // ---- conservative Allen-Cahn populations: BGK towards
@@ -898,17 +962,18 @@ __device__ __forceinline__ void collide_cell(const Planes<FS, GS>& pl, const T* 
     const T kc = pp.kc * ph * ((T)1 - ph) * inv_g;
     const T jv[3] = {ph * u[0] + kc * gr[0], ph * u[1] + kc * gr[1], ph * u[2] + kc * gr[2]};
     const T itp = pp.inv_tau_phi;
+    const PopNbr<GS> pg(pl.g, x, y, z, geo, QG);
     T gi[QG];
 #pragma unroll
     for (int k = 0; k < QG; ++k) {
-      const GS* gp = pl.g[PAR == 0 ? k : opp(k)];
-      const unsigned src = PAR == 0 ? idx : (unsigned)nb(-P::cx[k], -P::cy[k], -P::cz[k]);
-      gi[k] = (T)*plane_at<OFF32>(gp, src);
+      const GS* src = PAR == 0 ? pg.template at<OFF32>(k, 0, 0, 0)
+                               : pg.template at<OFF32>(opp(k), -P::cx[k], -P::cy[k], -P::cz[k]);
+      gi[k] = (T)*src;
     }
     // geq - g is formed with the product unrounded: a rounded w_k (phi + c.j/cs^2)
     // (the D2Q9 weights are not powers of two) would bias the phase-field mass
     // of every step, like weights that do not sum to one.
-    *plane_at<OFF32>(pl.g[0], idx) = (GS)fmad(fmad(wt<P, T>(0), ph, -gi[0]), itp, gi[0]);
+    *pg.template at<OFF32>(0, 0, 0, 0) = (GS)fmad(fmad(wt<P, T>(0), ph, -gi[0]), itp, gi[0]);
 #pragma unroll
     for (int k = 1; k < QG; k += 2) {
       const int cx = P::cx[k], cy = P::cy[k], cz = P::cz[k];
@@ -916,14 +981,12 @@ __device__ __forceinline__ void collide_cell(const Planes<FS, GS>& pl, const T* 
       const T wk = wt<P, T>(k);
       const T ga = fmad(fmad(wk, ph + cj, -gi[k]), itp, gi[k]);
       const T gb = fmad(fmad(wk, ph - cj, -gi[k + 1]), itp, gi[k + 1]);
-      GS* const pk = pl.g[k];
-      GS* const pk1 = pl.g[k + 1];
       if constexpr (PAR == 0) {
-        *plane_at<OFF32>(pk1, idx) = (GS)ga;
-        *plane_at<OFF32>(pk, idx) = (GS)gb;
+        *pg.template at<OFF32>(k + 1, 0, 0, 0) = (GS)ga;
+        *pg.template at<OFF32>(k, 0, 0, 0) = (GS)gb;
       } else {
-        *plane_at<OFF32>(pk, (unsigned)nb(cx, cy, cz)) = (GS)ga;
-        *plane_at<OFF32>(pk1, (unsigned)nb(-cx, -cy, -cz)) = (GS)gb;
+        *pg.template at<OFF32>(k, cx, cy, cz) = (GS)ga;
+        *pg.template at<OFF32>(k + 1, -cx, -cy, -cz) = (GS)gb;
       }
     }
   } else if (macro) {
@@ -980,7 +1043,7 @@ __global__ __launch_bounds__(NT) void k_collide(Planes<FS, GS> pl, const T* __re
                                                 double* __restrict__ partials) {
   if (nci_on && blockIdx.x == 0 && threadIdx.x == 0) *cnt_other = 0u;
   int x, y, z;
-  block_cell(swizzled_block(), geo, x, y, z);
+  block_cell(slab_block(geo), geo, x, y, z);
   const bool valid = x < geo.nx && y < geo.ny;
   double acc[NPART] = {};
   if (MODE == MODE_STEP && !valid) return;
@@ -1160,7 +1223,7 @@ __global__ __launch_bounds__(NT) void k_init(FS* __restrict__ f, GS* __restrict_
     const T cu = i == 0 ? (T)0 : sdot(H::cx[i], H::cy[i], H::cz[i], u[0], u[1], u[2]);
     const T fe = wt<H, T>(i) * (ps + (T)3 * cu + (T)4.5 * cu * cu - (T)1.5 * uu + (T)4.5 * cu * cu * cu -
                                (T)4.5 * cu * uu);
-    Store<FS>::st(f + i * S + idx, fe, pp.fref[i]);
+    Store<FS>::st(f + pop_elem(i, x, y, z, geo, H::Q), fe, pp.fref[i]);
   }
   T gr[3], lap;
   grad_lap<DIM, T>([&](int i) { return phi[nb(H::cx[i], H::cy[i], H::cz[i])]; }, gr, lap);
@@ -1171,7 +1234,7 @@ __global__ __launch_bounds__(NT) void k_init(FS* __restrict__ f, GS* __restrict_
 #pragma unroll
   for (int k = 0; k < P::Q; ++k) {
     const T cj = k == 0 ? (T)0 : sdot(P::cx[k], P::cy[k], P::cz[k], jv[0], jv[1], jv[2]);
-    g[k * S + idx] = (GS)(wt<P, T>(k) * (ph + cj * (T)P::inv_cs2));
+    g[pop_elem(k, x, y, z, geo, P::Q)] = (GS)(wt<P, T>(k) * (ph + cj * (T)P::inv_cs2));
   }
 }
 
@@ -1188,17 +1251,17 @@ __global__ __launch_bounds__(NT) void k_getpop(const FS* __restrict__ f, const G
   if (e >= B) return;
   const int lx = (int)(e % bxn), ly = (int)((e / bxn) % byn), lz = (int)(e / ((long long)bxn * byn));
   const int x = wrapi(x0 + lx, geo.nx), y = wrapi(y0 + ly, geo.ny), z = wrapi(z0 + lz, geo.nz);
-  const Nbr nb(x, y, z, geo);
-  const int idx = nb(0, 0, 0);
+  const PopNbr<const FS> pf(f, x, y, z, geo, H::Q);
+  const PopNbr<const GS> pg(g, x, y, z, geo, P::Q);
   for (int i = 0; i < H::Q; ++i) {
-    const int slot = PAR == 0 ? i : opp(i);
-    const int src = PAR == 0 ? idx : nb(-H::cx[i], -H::cy[i], -H::cz[i]);
-    fo[i * B + e] = (double)Store<FS>::ld(f + slot * geo.S + src, pp.fref[i]);
+    const FS* src = PAR == 0 ? pf.template at<false>(i, 0, 0, 0)
+                             : pf.template at<false>(opp(i), -H::cx[i], -H::cy[i], -H::cz[i]);
+    fo[i * B + e] = (double)Store<FS>::ld(src, pp.fref[i]);
   }
   for (int k = 0; k < P::Q; ++k) {
-    const int slot = PAR == 0 ? k : opp(k);
-    const int src = PAR == 0 ? idx : nb(-P::cx[k], -P::cy[k], -P::cz[k]);
-    go[k * B + e] = (double)g[slot * geo.S + src];
+    const GS* src = PAR == 0 ? pg.template at<false>(k, 0, 0, 0)
+                             : pg.template at<false>(opp(k), -P::cx[k], -P::cy[k], -P::cz[k]);
+    go[k * B + e] = (double)*src;
   }
 }
 
@@ -1212,9 +1275,10 @@ __global__ __launch_bounds__(NT) void k_setpop(FS* __restrict__ f, GS* __restric
   const long long N = (long long)geo.nx * geo.ny * geo.nz;
   const long long e = (long long)blockIdx.x * NT + threadIdx.x;
   if (e >= N) return;
+  const int x = (int)(e % geo.nx), y = (int)((e / geo.nx) % geo.ny), z = (int)(e / ((long long)geo.nx * geo.ny));
   for (int i = 0; i < H::Q; ++i)
-    Store<FS>::st(f + i * geo.S + e, (T)fi[i * N + e], pp.fref[i]);
-  for (int k = 0; k < P::Q; ++k) g[k * geo.S + e] = (GS)gi[k * N + e];
+    Store<FS>::st(f + pop_elem(i, x, y, z, geo, H::Q), (T)fi[i * N + e], pp.fref[i]);
+  for (int k = 0; k < P::Q; ++k) g[pop_elem(k, x, y, z, geo, P::Q)] = (GS)gi[k * N + e];
 }
 
 // ---------------------------------------------------------------------------
@@ -1266,10 +1330,10 @@ __global__ __launch_bounds__(NT) void k_phi_multi(const Job<T, FS, GS>* __restri
   block_cell(lb, jb.geo, x, y, z);
   if (x >= jb.geo.nx || y >= jb.geo.ny) return;
   if (par == 0)
-    phi_cell<DIM, 0, T, GS>(jb.pl.g[0], jb.phi, jb.geo, jb.flags[0], jb.list[0], jb.cnt, jb.nci_on,
+    phi_cell<DIM, 0, T, GS>(jb.pl.g, jb.phi, jb.geo, jb.flags[0], jb.list[0], jb.cnt, jb.nci_on,
                             jb.q_th, x, y, z);
   else
-    phi_cell<DIM, 1, T, GS>(jb.pl.g[0], jb.phi, jb.geo, jb.flags[1], jb.list[1], jb.cnt + 1,
+    phi_cell<DIM, 1, T, GS>(jb.pl.g, jb.phi, jb.geo, jb.flags[1], jb.list[1], jb.cnt + 1,
                             jb.nci_on, jb.q_th, x, y, z);
 }
 

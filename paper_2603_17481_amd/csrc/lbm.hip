@@ -49,6 +49,7 @@ void tile_dims(int dim, int prec, int* tx, int* ty, int* tz) {
 struct Layout {
   long long N, S;
   int nblk, ntiles, ttx, tty, ttz, ntx, nty, ntz;
+  int rs, qc;   // population chunks: 2^rs rows, qc = nx 2^rs cells
   size_t off_f, off_g, off_phi, off_J, off_flags, off_list, off_cnt, off_pa, off_pb, off_s1,
       off_red, off_lab, total;
 };
@@ -64,6 +65,7 @@ bool valid_params(const lbm_params* p, std::string* why) {
   if (p->dim == 2 && p->nz != 1) return bad("2D boxes need nz = 1");
   const long long N = (long long)p->nx * p->ny * p->nz;
   if (N >= (1LL << 31) - 4096) return bad("box too large (more than 2^31 cells)");
+  if ((long long)p->nx * p->ny * 19 >= (1LL << 32)) return bad("z plane too large (nx ny 19 must be below 2^32)");
   if (p->precision < LBM_FP64 || p->precision > LBM_FP32_BF16STORE) return bad("unknown precision");
   if (!(p->tau > 0.5)) return bad("tau must exceed 1/2");
   if (!(p->visc_ratio > 0)) return bad("visc_ratio must be positive");
@@ -89,6 +91,18 @@ Layout make_layout(const lbm_params* p) {
   // FP32), so that the 26 concurrent population streams do not start at the same
   // offset modulo large powers of two (+4 % on the collide kernel at 512^3).
   L.S = ((L.N + 127) & ~127LL) + 1088;
+  // Population chunks of about 8192 cells (2^rs rows; rs no larger than the
+  // power of two dividing ny, so no chunk is partial): a block's 26 population
+  // streams then fall into a few contiguous regions (+8 % streaming bandwidth
+  // over planes of the whole box, measured at 512^3).
+  {
+    int lg = 0;
+    while ((1 << lg) < p->nx) ++lg;
+    int tz = 0;
+    while (tz < 30 && ((p->ny >> tz) & 1) == 0) ++tz;
+    L.rs = std::min(std::max(0, 13 - lg), tz);
+    L.qc = p->nx << L.rs;
+  }
   const int nbx = (p->nx + BX - 1) / BX, nby = (p->ny + BY - 1) / BY;
   L.nblk = nbx * nby * p->nz;
   tile_dims(p->dim, p->precision, &L.ttx, &L.tty, &L.ttz);
@@ -98,8 +112,8 @@ Layout make_layout(const lbm_params* p) {
   L.ntiles = L.ntx * L.nty * L.ntz;
   const size_t rs = real_size(p->precision), fs = fstore_size(p->precision);
   size_t o = 0;
-  L.off_f = o;   o = align256(o + (size_t)q_hydro(p->dim) * L.S * fs);
-  L.off_g = o;   o = align256(o + (size_t)q_phase(p->dim) * L.S * rs);
+  L.off_f = o;   o = align256(o + (size_t)q_hydro(p->dim) * L.N * fs);
+  L.off_g = o;   o = align256(o + (size_t)q_phase(p->dim) * L.N * rs);
   L.off_phi = o; o = align256(o + (size_t)L.S * rs);
   L.off_J = o;   o = align256(o + (size_t)p->dim * L.S * rs);
   L.off_flags = o; o = align256(o + 2 * (size_t)L.ntiles * 4);
@@ -339,15 +353,18 @@ struct Engine {
 
   static Planes<FS, GS> planes(const lbm_ctx* c) {
     Planes<FS, GS> pl{};
-    for (int i = 0; i < Hydro<DIM>::Q; ++i) pl.f[i] = (FS*)c->f() + (size_t)i * c->L.S;
-    for (int k = 0; k < Phase<DIM>::Q; ++k) pl.g[k] = (GS*)c->g() + (size_t)k * c->L.S;
+    pl.f = (FS*)c->f();
+    pl.g = (GS*)c->g();
     return pl;
   }
 
-  // 32-bit byte offsets are used when every plane is below 4 GiB.
+  // 32-bit byte offsets are used when the populations of a z plane and every
+  // phi / J plane stay below 4 GiB.
   static bool off32(const lbm_ctx* c) {
-    const size_t widest = std::max(sizeof(FS), std::max(sizeof(GS), sizeof(T)));
-    return (size_t)c->L.S * widest < (size_t(1) << 32);
+    const size_t plane = (size_t)c->p.nx * c->p.ny;
+    const size_t widest = std::max(plane * Hydro<DIM>::Q * sizeof(FS),
+                                   std::max(plane * Phase<DIM>::Q * sizeof(GS), (size_t)c->L.S * sizeof(T)));
+    return widest < (size_t(1) << 32);
   }
 
   template <int MODE>
@@ -802,6 +819,8 @@ int lbm_create(const lbm_params* p, void* dev_workspace, size_t ws_bytes, void* 
   G.ntx = c->L.ntx;
   G.nty = c->L.nty;
   G.ntz = c->L.ntz;
+  G.rs = c->L.rs;
+  G.qc = c->L.qc;
   NciP& A = c->nci;
   A.a_rep = p->a_rep;
   A.q_th = p->q_th;
