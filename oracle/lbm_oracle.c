@@ -350,6 +350,7 @@ struct oracle_state {
   lattice LF, LG;
   double *f, *f2, *g, *g2;                     /* AoS: f[idx*q + i] */
   double *phi, *grad, *lap, *nrm, *q, *mu;     /* per cell, vectors SoA [a*N + idx] */
+  double *phi2, *acomp;                        /* MUSCL mode: next phi, compressive flux */
   double *J;
   int *chi, *partner;
   double *pstar, *rho, *u, *F, *omega, *nu;
@@ -384,6 +385,8 @@ oracle_state* oracle_create(const oracle_params* p) {
   s->g = dalloc(N * s->LG.q);
   s->g2 = dalloc(N * s->LG.q);
   s->phi = dalloc(N);
+  s->phi2 = dalloc(N);
+  s->acomp = dalloc(3 * N);
   s->grad = dalloc(3 * N);
   s->lap = dalloc(N);
   s->nrm = dalloc(3 * N);
@@ -398,7 +401,8 @@ oracle_state* oracle_create(const oracle_params* p) {
   s->F = dalloc(3 * N);
   s->omega = dalloc(N);
   s->nu = dalloc(N);
-  if (!s->f || !s->f2 || !s->g || !s->g2 || !s->phi || !s->grad || !s->lap || !s->nrm || !s->q ||
+  if (!s->f || !s->f2 || !s->g || !s->g2 || !s->phi || !s->phi2 || !s->acomp || !s->grad || !s->lap ||
+      !s->nrm || !s->q ||
       !s->mu || !s->J || !s->chi || !s->partner || !s->pstar || !s->rho || !s->u || !s->F ||
       !s->omega || !s->nu) {
     oracle_destroy(s);
@@ -416,7 +420,8 @@ oracle_state* oracle_create(const oracle_params* p) {
 void oracle_destroy(oracle_state* s) {
   if (!s) return;
   free(s->f); free(s->f2); free(s->g); free(s->g2);
-  free(s->phi); free(s->grad); free(s->lap); free(s->nrm); free(s->q); free(s->mu);
+  free(s->phi); free(s->phi2); free(s->acomp);
+  free(s->grad); free(s->lap); free(s->nrm); free(s->q); free(s->mu);
   free(s->J); free(s->chi); free(s->partner);
   free(s->pstar); free(s->rho); free(s->u); free(s->F); free(s->omega); free(s->nu);
   free(s);
@@ -435,8 +440,10 @@ static long nb(const oracle_state* s, long idx, const int* c) {
   return wrapi(x + c[0], s->nx) + s->nx * (wrapi(y + c[1], s->ny) + s->ny * wrapi(z + c[2], s->nz));
 }
 
-/* Step 1: phi = sum_i g_i. */
+/* Step 1: phi = sum_i g_i (lattice Boltzmann phase field; with the finite-
+ * difference solver phi is itself the stored field and is left as it is). */
 static void compute_phi(oracle_state* s) {
+  if (s->P.cac_solver != 0) return;
 #pragma omp parallel for schedule(static)
   for (long idx = 0; idx < s->N; ++idx) {
     double a = 0.0;
@@ -579,6 +586,7 @@ static void collide_and_push(oracle_state* s) {
       double post = feq[i] + (1.0 - omega) * R[i] + 0.5 * S[i];
       s->f2[nb(s, idx, L->c[i]) * Q + i] = post;
     }
+    if (s->P.cac_solver != 0) continue;   /* MUSCL mode: no phase-field populations */
     double ph = s->phi[idx];
     double j[3] = {0, 0, 0};
     for (int a = 0; a < D; ++a) j[a] = ph * u[a] + comp * M * (4.0 / W) * ph * (1.0 - ph) * nv[a];
@@ -635,6 +643,75 @@ static void round_storage(oracle_state* s) {
   const long nf = s->N * s->LF.q, ng = s->N * s->LG.q;
   for (long i = 0; i < nf; ++i) s->f[i] = round_to(s->f[i], mode);
   for (long i = 0; i < ng; ++i) s->g[i] = round_to(s->g[i], 1);
+  if (s->P.cac_solver != 0)   /* MUSCL mode: the stored phase field is the phi array */
+    for (long i = 0; i < s->N; ++i) s->phi[i] = round_to(s->phi[i], 1);
+}
+
+/* Eq. minmod */
+static double minmod(double a, double b) {
+  if (a * b <= 0.0) return 0.0;
+  return (a > 0.0 ? 1.0 : -1.0) * (fabs(a) < fabs(b) ? fabs(a) : fabs(b));
+}
+
+/* Advective flux through the face between cell c0 and its neighbour c1 = c0 + e_ax
+ * (Eqs. face_flux_def, slope_minmod_x, recon_lr_x, upwind_select_x): face velocity
+ * the mean of the two cells' velocities, phi from the limited linear reconstruction
+ * on the upwind side. */
+static double face_flux(const oracle_state* s, long c0, int ax) {
+  int e[3] = {0, 0, 0};
+  e[ax] = 1;
+  int me[3] = {0, 0, 0};
+  me[ax] = -1;
+  const long N = s->N;
+  const long c1 = nb(s, c0, e);
+  const long cm = nb(s, c0, me);
+  const long c2 = nb(s, c1, e);
+  const double* p = s->phi;
+  const double uf = 0.5 * (s->u[ax * N + c0] + s->u[ax * N + c1]);
+  const double s0 = minmod(p[c0] - p[cm], p[c1] - p[c0]);
+  const double s1 = minmod(p[c1] - p[c0], p[c2] - p[c1]);
+  const double phL = p[c0] + 0.5 * s0;
+  const double phR = p[c1] - 0.5 * s1;
+  return uf * (uf >= 0.0 ? phL : phR);
+}
+
+/* One explicit step of the conservative Allen-Cahn equation by finite differences
+ * (Sec. 2.1.1, Eq. phi_update_muscl), every term from time level n:
+ *   phi' = phi - div_h(u phi) + D lap_h(phi) + S_comp,
+ * div_h(u phi) from the face fluxes above (Eq. divF), D = M, lap_h the isotropic
+ * lattice Laplacian (Eq. lap_iso), and S_comp = -kappa div_iso(phi (1 - phi) n) with
+ * kappa = 4 M / W (Eq. kappa_delta) and div_iso(a) = (1/cs^2) sum_i w_i c_i . a(x + c_i)
+ * the isotropic divergence on the hydrodynamic lattice (Eq. source_sharp). */
+static void muscl_update(oracle_state* s) {
+  const lattice* L = &s->LF;
+  const int D = s->D;
+  const long N = s->N;
+  const double M = s->P.mobility, W = s->P.width;
+  const double kappa = (s->P.cac_compress ? 1.0 : 0.0) * 4.0 * M / W;
+#pragma omp parallel for schedule(static)
+  for (long idx = 0; idx < N; ++idx) {
+    const double ph = s->phi[idx];
+    for (int a = 0; a < D; ++a) s->acomp[a * N + idx] = ph * (1.0 - ph) * s->nrm[a * N + idx];
+  }
+#pragma omp parallel for schedule(static)
+  for (long idx = 0; idx < N; ++idx) {
+    double div = 0.0;
+    for (int ax = 0; ax < D; ++ax) {
+      int me[3] = {0, 0, 0};
+      me[ax] = -1;
+      div += face_flux(s, idx, ax) - face_flux(s, nb(s, idx, me), ax);
+    }
+    double divc = 0.0;
+    for (int i = 0; i < L->q; ++i) {
+      const long y = nb(s, idx, L->c[i]);
+      for (int a = 0; a < D; ++a) divc += L->w[i] * L->c[i][a] * s->acomp[a * N + y];
+    }
+    divc /= L->cs2;
+    s->phi2[idx] = s->phi[idx] - div + M * s->lap[idx] - kappa * divc;
+  }
+  double* t = s->phi;
+  s->phi = s->phi2;
+  s->phi2 = t;
 }
 
 int oracle_step(oracle_state* s, int n) {
@@ -642,6 +719,7 @@ int oracle_step(oracle_state* s, int n) {
   for (int k = 0; k < n; ++k) {
     compute_fields(s);
     collide_and_push(s);
+    if (s->P.cac_solver != 0) muscl_update(s);
     round_storage(s);
     s->step++;
   }

@@ -33,6 +33,9 @@ typedef struct {
   int rep_orient;          /* 0: along n(x); +1: toward partner; -1: away from partner  */
   int dispersed;           /* 1: droplets {phi>1/2}; 0: bubbles {phi<1/2}; -1: auto     */
   int cac_compress;        /* 1: counter-gradient flux on; 0: off (pure diffusion)       */
+  int cac_solver;          /* phase field: 0 conservative Allen-Cahn lattice Boltzmann
+                              (g populations); 1 finite-difference MUSCL-TVD update of
+                              phi (Sec. 2.1.1, Eq. phi_update_muscl)                   */
   int store_round;         /* test knob: 0 none; round stored populations after each
                               step to 1 float32, 2 half (f), 3 bfloat16 (f)            */
 } oracle_params;

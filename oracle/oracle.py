@@ -26,7 +26,7 @@ class _Params(C.Structure):
         ("p_exp", C.c_double), ("eps_n", C.c_double), ("eps_q", C.c_double),
         ("tie_eps", C.c_double),
         ("rep_orient", C.c_int), ("dispersed", C.c_int), ("cac_compress", C.c_int),
-        ("store_round", C.c_int),
+        ("cac_solver", C.c_int), ("store_round", C.c_int),
     ]
 
 
@@ -111,6 +111,7 @@ def make_params(p, store_round: int = 0) -> _Params:
     s.p_exp, s.eps_n, s.eps_q = p.p_exp, p.eps_n, p.eps_q
     s.tie_eps = p.tie_eps
     s.rep_orient, s.dispersed, s.cac_compress = p.rep_orient, p.dispersed, p.cac_compress
+    s.cac_solver = p.cac_solver
     s.store_round = int(store_round)
     return s
 

@@ -57,6 +57,7 @@ class Params:
     rep_orient: int = 0          # 0: along n(x); +1: toward partner; -1: away from partner
     dispersed: int = -1          # 1: droplets {phi>1/2}; 0: bubbles {phi<1/2}; -1: minority phase
     cac_compress: int = 1        # 0 switches the counter-gradient flux off (diffusion test)
+    cac_solver: int = 0          # phase field: 0 lattice Boltzmann (g), 1 finite-difference MUSCL-TVD
     diag_interval: int = 0       # periodic on-device diagnostics every K steps (0: never)
     pstar_ref: float = 0.0       # reference p* of the 16-bit population encoding
 
