@@ -82,6 +82,13 @@ typedef struct {
   int cac_compress;          /* 1: counter-gradient flux on; 0: off (pure diffusion)        */
   int diag_interval;         /* K > 0: on-device diagnostics every K steps inside lbm_step  */
   double pstar_ref;          /* reference p* of the 16-bit population encoding              */
+  int cac_solver;            /* phase-field solver: 0 the lattice Boltzmann scheme of
+                                Sec. 2.1.2 (populations g, D2Q9 / D3Q7); 1 the explicit
+                                finite-difference scheme of Sec. 2.1.1 (Eq.
+                                phi_update_muscl: MUSCL reconstruction with the minmod
+                                limiter, upwind face fluxes, isotropic Laplacian and
+                                sharpening divergence), phi stored and double-buffered.
+                                Not supported by lbm_batch_step.                        */
 } lbm_params;
 
 typedef struct {
@@ -160,10 +167,11 @@ int lbm_diagnostics(lbm_ctx* ctx, lbm_diag* out);
 int lbm_diag_history(lbm_ctx* ctx, lbm_diag* out, int max);
 
 /* Per-kernel timing with HIP events recorded on the context's stream around
- * every launch lbm_step makes (0 phi moment, 1 near-contact, 2 collide +
- * stream, 3 diagnostics).  lbm_timing(ctx, 1) starts recording, 0 stops;
+ * every launch lbm_step makes (0 phi moment and interface flags, 1
+ * near-contact, 2 collide + stream, 3 diagnostics, 4 finite-difference phase
+ * field update).  lbm_timing(ctx, 1) starts recording, 0 stops;
  * lbm_kernel_times synchronises, returns the accumulated milliseconds and
- * launch counts since the last call (ms[4], counts[4]) and resets them. */
+ * launch counts since the last call (ms[5], counts[5]) and resets them. */
 int lbm_timing(lbm_ctx* ctx, int enable);
 int lbm_kernel_times(lbm_ctx* ctx, double* ms, long* counts);
 
@@ -176,11 +184,14 @@ int lbm_lattice(int dim, int which, int* c);
 int lbm_get_populations(lbm_ctx* ctx, int x0, int y0, int z0, int bx, int by, int bz,
                         double* f, double* g);
 /* Replace the whole state by the given incoming populations (SoA [q][N]); the
- * step count becomes 0.  Synchronous. */
+ * step count becomes 0.  Synchronous.  LBM_E_UNSUPPORTED with the
+ * finite-difference phase field (cac_solver 1), whose state is f and phi; its
+ * g, as lbm_get_populations returns them, stay as lbm_init_fields set them. */
 int lbm_set_populations(lbm_ctx* ctx, const double* f, const double* g);
 
-/* Raw state (populations in their stored precision and AA layout, step count)
- * for checkpoint / restart; a restored context continues bit for bit. */
+/* Raw state (populations in their stored precision and AA layout, step count;
+ * with cac_solver 1 also phi) for checkpoint / restart; a restored context
+ * continues bit for bit. */
 size_t lbm_state_bytes(const lbm_ctx* ctx);
 int lbm_save_state(lbm_ctx* ctx, void* host_buf, size_t bytes);
 int lbm_load_state(lbm_ctx* ctx, const void* host_buf, size_t bytes);

@@ -300,7 +300,7 @@ __device__ __forceinline__ T wave_min(T v) {
 // phi of one cell from its incoming phase-field populations (AA parity PAR),
 // accumulated in FP64 (exact for FP32 populations) and rounded once; an
 // interfacial cell flags and lists its near-contact tile.
-template <int DIM, int PAR, typename T, typename GS>
+template <int DIM, int PAR, typename T, typename GS, bool GIVEN = false>
 __device__ __forceinline__ void phi_cell(const GS* __restrict__ g, T* __restrict__ phi, const Geo& geo,
                                          unsigned* __restrict__ flags, unsigned* __restrict__ list,
                                          unsigned* __restrict__ cnt, int nci_on, T q_th, int x, int y,
@@ -308,17 +308,23 @@ __device__ __forceinline__ void phi_cell(const GS* __restrict__ g, T* __restrict
   using P = Phase<DIM>;
   using TL = NciTile<DIM, T>;
   const int idx = x + geo.nx * (y + geo.ny * z);
-  double acc = 0.0;
-  const PopNbr<const GS> pn(g, x, y, z, geo, P::Q);
-  if constexpr (PAR == 0) {
-#pragma unroll
-    for (int i = 0; i < P::Q; ++i) acc += (double)*pn.template at<false>(i, 0, 0, 0);
+  T s;
+  if constexpr (GIVEN) {
+    s = phi[idx];   // finite-difference phase field: phi is the stored field
   } else {
+    double acc = 0.0;
+    const PopNbr<const GS> pn(g, x, y, z, geo, P::Q);
+    if constexpr (PAR == 0) {
 #pragma unroll
-    for (int i = 0; i < P::Q; ++i) acc += (double)*pn.template at<false>(opp(i), -P::cx[i], -P::cy[i], -P::cz[i]);
+      for (int i = 0; i < P::Q; ++i) acc += (double)*pn.template at<false>(i, 0, 0, 0);
+    } else {
+#pragma unroll
+      for (int i = 0; i < P::Q; ++i)
+        acc += (double)*pn.template at<false>(opp(i), -P::cx[i], -P::cy[i], -P::cz[i]);
+    }
+    s = (T)acc;
+    phi[idx] = s;
   }
-  const T s = (T)acc;
-  phi[idx] = s;
   if (nci_on) {
     const T pc = s < (T)0 ? (T)0 : (s > (T)1 ? (T)1 : s);
     const T q = pc * ((T)1 - pc);
@@ -354,7 +360,7 @@ __device__ __forceinline__ void block_cell(int t, const Geo& geo, int& x, int& y
   y = by * BY + (int)(threadIdx.x / BX);
 }
 
-template <int DIM, int PAR, typename T, typename GS>
+template <int DIM, int PAR, typename T, typename GS, bool GIVEN>
 __global__ __launch_bounds__(NT) void k_phi(const GS* __restrict__ g, T* __restrict__ phi, Geo geo,
                                             unsigned* __restrict__ flags,
                                             unsigned* __restrict__ list,
@@ -364,7 +370,7 @@ __global__ __launch_bounds__(NT) void k_phi(const GS* __restrict__ g, T* __restr
   int x, y, z;
   block_cell(swizzled_block(), geo, x, y, z);
   if (x >= geo.nx || y >= geo.ny) return;
-  phi_cell<DIM, PAR, T, GS>(g, phi, geo, flags, list, cnt, nci_on, q_th, x, y, z);
+  phi_cell<DIM, PAR, T, GS, GIVEN>(g, phi, geo, flags, list, cnt, nci_on, q_th, x, y, z);
 }
 
 // ---------------------------------------------------------------------------
@@ -823,7 +829,8 @@ __device__ __forceinline__ void collide_cell(const Planes<FS, GS>& pl, const T* 
                                              const T* __restrict__ J,
                                              const unsigned* __restrict__ flags, const Geo& geo,
                                              const PhysT<T>& pp, int nci_on, T* __restrict__ macro,
-                                             int x, int y, int z, double acc[NPART]) {
+                                             T* __restrict__ uout, int x, int y, int z,
+                                             double acc[NPART]) {
   using H = Hydro<DIM>;
   using P = Phase<DIM>;
   using TL = NciTile<DIM, T>;
@@ -957,6 +964,16 @@ __device__ __forceinline__ void collide_cell(const Planes<FS, GS>& pl, const T* 
         Store<FS>::st(pf.template at<OFF32>(i + 1, -cx, -cy, -cz), fb, pp.fref[i]);
       }
     }
+    if (uout) {
+      // finite-difference phase field: the velocity of this collision and the
+      // sharpening flux a = phi (1 - phi) n feed the explicit update
+      const T kn = ph * ((T)1 - ph) * inv_g;
+#pragma unroll
+      for (int a = 0; a < DIM; ++a) {
+        uout[a * S + idx] = u[a];
+        uout[(DIM + a) * S + idx] = kn * gr[a];
+      }
+    } else {
     // ---- conservative Allen-Cahn populations: BGK towards
     //      geq_k = w_k (phi + c_k . j / cs_phi^2), j = phi u + M (4/W) phi (1-phi) n
     const T kc = pp.kc * ph * ((T)1 - ph) * inv_g;
@@ -988,6 +1005,7 @@ __device__ __forceinline__ void collide_cell(const Planes<FS, GS>& pl, const T* 
         *pg.template at<OFF32>(k, cx, cy, cz) = (GS)ga;
         *pg.template at<OFF32>(k + 1, -cx, -cy, -cz) = (GS)gb;
       }
+    }
     }
   } else if (macro) {
     // dry evaluation: macroscopic fields of the current state
@@ -1040,15 +1058,105 @@ __global__ __launch_bounds__(NT) void k_collide(Planes<FS, GS> pl, const T* __re
                                                 const unsigned* __restrict__ flags,
                                                 unsigned* __restrict__ cnt_other, Geo geo,
                                                 PhysT<T> pp, int nci_on, T* __restrict__ macro,
-                                                double* __restrict__ partials) {
+                                                T* __restrict__ uout, double* __restrict__ partials) {
   if (nci_on && blockIdx.x == 0 && threadIdx.x == 0) *cnt_other = 0u;
   int x, y, z;
   block_cell(slab_block(geo), geo, x, y, z);
   const bool valid = x < geo.nx && y < geo.ny;
   double acc[NPART] = {};
   if (MODE == MODE_STEP && !valid) return;
-  if (valid) collide_cell<DIM, PAR, MODE, T, FS, GS, OFF32>(pl, phi, J, flags, geo, pp, nci_on, macro, x, y, z, acc);
+  if (valid) collide_cell<DIM, PAR, MODE, T, FS, GS, OFF32>(pl, phi, J, flags, geo, pp, nci_on, macro, uout, x, y, z, acc);
   if constexpr (MODE != MODE_STEP) block_partials(acc, partials);
+}
+
+// ---------------------------------------------------------------------------
+// (b2) finite-difference phase field (Sec. 2.1.1): one explicit step of the
+//      conservative Allen-Cahn equation, Eq. phi_update_muscl
+// ---------------------------------------------------------------------------
+
+// Periodic coordinate for offsets of at most two cells (any n >= 1).
+__device__ __forceinline__ int wrap2(int v, int n) {
+  if (v < 0) v += n;
+  if (v < 0) v += n;
+  if (v >= n) v -= n;
+  if (v >= n) v -= n;
+  return v;
+}
+
+// Eq. minmod: the smaller slope when both have the same sign, else zero.
+template <typename T>
+__device__ __forceinline__ T minmod(T a, T b) {
+  if (a * b <= (T)0) return (T)0;
+  const T m = fabs(a) < fabs(b) ? fabs(a) : fabs(b);
+  return a > (T)0 ? m : -m;
+}
+
+// Advective flux through the face between cells 0 and 1 (Eqs. face_flux_def,
+// slope_minmod_x, recon_lr_x, upwind_select_x): phi reconstructed linearly
+// with limited slopes on each side (pm and p2 are the outer neighbours of
+// cells 0 and 1) and taken from the upwind side of the face velocity uf.
+template <typename T>
+__device__ __forceinline__ T face_flux(T pm, T p0, T p1, T p2, T uf) {
+  const T phL = p0 + (T)0.5 * minmod(p0 - pm, p1 - p0);
+  const T phR = p1 - (T)0.5 * minmod(p1 - p0, p2 - p1);
+  return uf * (uf >= (T)0 ? phL : phR);
+}
+
+// phi' = phi - div_h(u phi) + M lap_h phi - kappa div_iso(a), every term from
+// the state before the step: u the velocity of that state's collision, the
+// face velocity the mean of the two cells', lap_h the isotropic Laplacian
+// (Eq. lap_iso), a = phi (1 - phi) n written by the collision, div_iso(a) =
+// (1/cs^2) sum_i w_i c_i . a(x + c_i) on the hydrodynamic lattice and kappa =
+// 4 M / W (Eqs. source_sharp, kappa_delta).  ua holds u (DIM planes) then a
+// (DIM planes), plane stride S; out must not alias phi.
+template <int DIM, typename T>
+__global__ __launch_bounds__(NT) void k_muscl(const T* __restrict__ phi, T* __restrict__ out,
+                                              const T* __restrict__ ua, Geo geo, T mob, T kap) {
+  using H = Hydro<DIM>;
+  int x, y, z;
+  block_cell(swizzled_block(), geo, x, y, z);
+  if (x >= geo.nx || y >= geo.ny) return;
+  const long long S = geo.S;
+  const Nbr nb(x, y, z, geo);
+  const int idx = nb(0, 0, 0);
+  const int cc[3] = {x, y, z};
+  const int nn[3] = {geo.nx, geo.ny, geo.nz};
+  const int st[3] = {1, geo.nx, geo.nx * geo.ny};
+  T div = 0;
+#pragma unroll
+  for (int ax = 0; ax < DIM; ++ax) {
+    int o[5];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) o[k] = idx + (wrap2(cc[ax] + k - 2, nn[ax]) - cc[ax]) * st[ax];
+    const T p0 = phi[o[0]], p1 = phi[o[1]], p2 = phi[o[2]], p3 = phi[o[3]], p4 = phi[o[4]];
+    const T* U = ua + ax * S;
+    const T um = U[o[1]], u0 = U[o[2]], up = U[o[3]];
+    const T fp = face_flux(p1, p2, p3, p4, (T)0.5 * (u0 + up));
+    const T fm = face_flux(p0, p1, p2, p3, (T)0.5 * (um + u0));
+    div += fp - fm;
+  }
+  // Laplacian summed over differences to the cell (Eq. lap_iso), so that it
+  // vanishes exactly on a uniform field: the rounded weights sum to one only
+  // approximately, and that residue would otherwise add mass every step.
+  const T* A = ua + DIM * S;
+  const T pc = phi[idx];
+  T sl = 0, dc = 0;
+#pragma unroll
+  for (int i = 1; i < H::Q; i += 2) {
+    const int c[3] = {H::cx[i], H::cy[i], H::cz[i]};
+    const int yp = nb(c[0], c[1], c[2]), ym = nb(-c[0], -c[1], -c[2]);
+    const T w = wt<H, T>(i);
+    sl += w * ((phi[yp] - pc) + (phi[ym] - pc));
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+      if (!c[a]) continue;
+      const T d = w * (A[a * S + yp] - A[a * S + ym]);
+      dc += c[a] > 0 ? d : -d;
+    }
+  }
+  // The increment is formed first and added once: added term by term, the
+  // parts smaller than half an ulp of phi would each be rounded away.
+  out[idx] = pc + ((mob * ((T)6 * sl) - div) - kap * ((T)3 * dc));
 }
 
 // ---------------------------------------------------------------------------
@@ -1369,10 +1477,10 @@ __global__ __launch_bounds__(NT) void k_collide_multi(const Job<T, FS, GS>* __re
   double acc[NPART];
   if (par == 0)
     collide_cell<DIM, 0, MODE_STEP, T, FS, GS, OFF32>(jb.pl, jb.phi, jb.J, jb.flags[0], jb.geo, jb.pp,
-                                                      jb.nci_on, nullptr, x, y, z, acc);
+                                                      jb.nci_on, nullptr, nullptr, x, y, z, acc);
   else
     collide_cell<DIM, 1, MODE_STEP, T, FS, GS, OFF32>(jb.pl, jb.phi, jb.J, jb.flags[1], jb.geo, jb.pp,
-                                                      jb.nci_on, nullptr, x, y, z, acc);
+                                                      jb.nci_on, nullptr, nullptr, x, y, z, acc);
 }
 
 // Advances the step counter of every lattice of the table (end of a replay).

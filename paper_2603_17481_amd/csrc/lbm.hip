@@ -51,7 +51,7 @@ struct Layout {
   int nblk, ntiles, ttx, tty, ttz, ntx, nty, ntz;
   int rs, qc;   // population chunks: 2^rs rows, qc = nx 2^rs cells
   size_t off_f, off_g, off_phi, off_J, off_flags, off_list, off_cnt, off_pa, off_pb, off_s1,
-      off_red, off_lab, total;
+      off_red, off_lab, off_phi2, off_ua, total;
 };
 
 bool valid_params(const lbm_params* p, std::string* why) {
@@ -81,6 +81,7 @@ bool valid_params(const lbm_params* p, std::string* why) {
   if (p->rep_orient < -1 || p->rep_orient > 1) return bad("rep_orient must be -1, 0 or 1");
   if (p->dispersed < -1 || p->dispersed > 1) return bad("dispersed must be -1, 0 or 1");
   if (p->diag_interval < 0) return bad("diag_interval must be >= 0");
+  if (p->cac_solver != 0 && p->cac_solver != 1) return bad("cac_solver must be 0 or 1");
   return true;
 }
 
@@ -124,6 +125,10 @@ Layout make_layout(const lbm_params* p) {
   L.off_s1 = o;    o = align256(o + 2 * (size_t)RED1 * NPART * 8);
   L.off_red = o;   o = align256(o + (size_t)(HIST + 1) * 2 * NPART * 8);
   L.off_lab = o;   o = align256(o + (size_t)L.N * 4);
+  // finite-difference phase field only: the second phi buffer and u, a planes
+  const bool fd = p->cac_solver != 0;
+  L.off_phi2 = o;  o = align256(o + (fd ? (size_t)L.S * rs : 0));
+  L.off_ua = o;    o = align256(o + (fd ? 2 * (size_t)p->dim * L.S * rs : 0));
   L.total = o;
   return L;
 }
@@ -152,12 +157,16 @@ struct lbm_ctx {
   std::vector<hipEvent_t> ev;      // pairs (start, stop)
   std::vector<int> ev_kind;
   int ev_used = 0;
-  double k_ms[4] = {0, 0, 0, 0};
-  long k_cnt[4] = {0, 0, 0, 0};
+  double k_ms[5] = {0, 0, 0, 0, 0};
+  long k_cnt[5] = {0, 0, 0, 0, 0};
+  int phi_cur = 0;   // finite-difference phase field: which phi buffer holds the state
 
   void* f() const { return ws + L.off_f; }
   void* g() const { return ws + L.off_g; }
-  void* phi() const { return ws + L.off_phi; }
+  void* phi() const { return ws + (phi_cur ? L.off_phi2 : L.off_phi); }
+  void* phi_next() const { return ws + (phi_cur ? L.off_phi : L.off_phi2); }
+  void* ua() const { return ws + L.off_ua; }
+  bool fd() const { return p.cac_solver != 0; }
   void* J() const { return ws + L.off_J; }
   unsigned* flags(int k) const { return (unsigned*)(ws + L.off_flags) + (size_t)k * L.ntiles; }
   unsigned* list(int k) const { return (unsigned*)(ws + L.off_list) + (size_t)k * L.ntiles; }
@@ -327,7 +336,9 @@ struct Engine {
   // interfacial tile list of this parity.
   static void phi_pass(lbm_ctx* c, int par) {
     const int nci = c->nci_on() ? 1 : 0;
-    auto k = par == 0 ? k_phi<DIM, 0, T, GS> : k_phi<DIM, 1, T, GS>;
+    // with the finite-difference phase field phi is the state: flags only
+    auto k = c->fd() ? k_phi<DIM, 0, T, GS, true>
+                     : (par == 0 ? k_phi<DIM, 0, T, GS, false> : k_phi<DIM, 1, T, GS, false>);
     Timed tm(c, 0);
     hipLaunchKernelGGL(k, rows(c), dim3(NT), 0, c->stream, (const GS*)c->g(), (T*)c->phi(), c->geo,
                        c->flags(par), c->list(par), c->cnt() + par, c->cnt() + 2, nci,
@@ -375,7 +386,20 @@ struct Engine {
     Timed tm(c, 2);
     hipLaunchKernelGGL(k, rows(c), dim3(NT), 0, c->stream, planes(c),
                        (const T*)c->phi(), (const T*)c->J(), (const unsigned*)c->flags(par),
-                       c->cnt() + (1 - par), c->geo, physT(c), c->nci_on() ? 1 : 0, macro, c->pa());
+                       c->cnt() + (1 - par), c->geo, physT(c), c->nci_on() ? 1 : 0, macro,
+                       (MODE != MODE_DRY && c->fd()) ? (T*)c->ua() : (T*)nullptr, c->pa());
+  }
+
+  // Finite-difference phase field: phi of the next state into the other buffer.
+  static void muscl_pass(lbm_ctx* c) {
+    if (!c->fd()) return;
+    const double kap = c->p.cac_compress ? 4.0 * c->p.mobility / c->p.width : 0.0;
+    {
+      Timed tm(c, 4);
+      hipLaunchKernelGGL((k_muscl<DIM, T>), rows(c), dim3(NT), 0, c->stream, (const T*)c->phi(),
+                         (T*)c->phi_next(), (const T*)c->ua(), c->geo, (T)c->p.mobility, (T)kap);
+    }
+    c->phi_cur ^= 1;
   }
 
   static void diag_finish(lbm_ctx* c, int slot) {
@@ -411,6 +435,7 @@ struct Engine {
       } else {
         collide_pass<MODE_STEP>(c, par, nullptr);
       }
+      muscl_pass(c);
       c->step++;
     }
     hipError_t e = hipGetLastError();
@@ -865,6 +890,7 @@ int lbm_init_fields(lbm_ctx* c, const double* phi, const double* u, const double
   set_phys(c, mean_phi);
   c->dispersed = c->p.dispersed >= 0 ? c->p.dispersed : (mean_phi < 0.5 ? 1 : 0);
   reset_nci_state(c);
+  c->phi_cur = 0;
   const int rc = dispatch(c, [&](auto E) { return decltype(E)::init(c, phi, u, pstar); });
   if (rc != LBM_OK) return rc;
   c->step = 0;
@@ -989,6 +1015,8 @@ int lbm_get_populations(lbm_ctx* c, int x0, int y0, int z0, int bx, int by, int 
 int lbm_set_populations(lbm_ctx* c, const double* f, const double* g) {
   if (!c) return LBM_E_INVALID;
   if (!f || !g) return c->fail(LBM_E_INVALID, "null populations");
+  if (c->fd())
+    return c->fail(LBM_E_UNSUPPORTED, "the finite-difference phase field has no populations g to set");
   // mean phi (for the buoyancy reference) from the phase-field populations
   const long long N = c->L.N;
   const int qg = q_phase(c->p.dim);
@@ -1023,9 +1051,15 @@ constexpr unsigned long long STATE_MAGIC = 0x4c424d5354415445ULL;  // "LBMSTATE"
 size_t pop_bytes(const lbm_ctx* c) {
   return c->L.off_phi;  // f and g are the first two regions of the workspace
 }
+// the finite-difference phase field keeps phi itself as state
+size_t phi_state_bytes(const lbm_ctx* c) {
+  return c->fd() ? (size_t)c->L.N * real_size(c->p.precision) : 0;
+}
 }  // namespace
 
-size_t lbm_state_bytes(const lbm_ctx* c) { return c ? sizeof(StateHeader) + pop_bytes(c) : 0; }
+size_t lbm_state_bytes(const lbm_ctx* c) {
+  return c ? sizeof(StateHeader) + pop_bytes(c) + phi_state_bytes(c) : 0;
+}
 
 int lbm_save_state(lbm_ctx* c, void* buf, size_t bytes) {
   NEED_INIT(c);
@@ -1035,6 +1069,9 @@ int lbm_save_state(lbm_ctx* c, void* buf, size_t bytes) {
   std::memcpy(buf, &h, sizeof(h));
   HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
   HIP_OR_FAIL(c, hipMemcpy((char*)buf + sizeof(h), c->ws, pop_bytes(c), hipMemcpyDeviceToHost));
+  if (c->fd())
+    HIP_OR_FAIL(c, hipMemcpy((char*)buf + sizeof(h) + pop_bytes(c), c->phi(), phi_state_bytes(c),
+                             hipMemcpyDeviceToHost));
   return LBM_OK;
 }
 
@@ -1048,6 +1085,10 @@ int lbm_load_state(lbm_ctx* c, const void* buf, size_t bytes) {
     return c->fail(LBM_E_INVALID, "state does not match this context");
   HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
   HIP_OR_FAIL(c, hipMemcpy(c->ws, (const char*)buf + sizeof(h), pop_bytes(c), hipMemcpyHostToDevice));
+  c->phi_cur = 0;
+  if (c->fd())
+    HIP_OR_FAIL(c, hipMemcpy(c->phi(), (const char*)buf + sizeof(h) + pop_bytes(c), phi_state_bytes(c),
+                             hipMemcpyHostToDevice));
   c->step = h.step;
   c->dispersed = (int)h.dispersed;
   c->phys.rho_mean = h.rho_mean;
@@ -1077,7 +1118,7 @@ int lbm_kernel_times(lbm_ctx* c, double* ms, long* counts) {
   if (!c || !ms || !counts) return LBM_E_INVALID;
   const int rc = flush_timing(c);
   if (rc != LBM_OK) return rc;
-  for (int k = 0; k < 4; ++k) {
+  for (int k = 0; k < 5; ++k) {
     ms[k] = c->k_ms[k];
     counts[k] = c->k_cnt[k];
     c->k_ms[k] = 0.0;
@@ -1095,6 +1136,8 @@ int lbm_batch_step(lbm_ctx* const* ctxs, int count, int n) {
     lbm_ctx* c = ctxs[i];
     if (!c) return c0->fail(LBM_E_INVALID, "null context in batch");
     if (!c->initialised) return c0->fail(LBM_E_STATE, "batch holds an uninitialised context");
+    if (c->fd())
+      return c0->fail(LBM_E_UNSUPPORTED, "batches step the lattice Boltzmann phase field only (cac_solver 0)");
     if (c->dev != c0->dev || c->p.dim != c0->p.dim || c->p.precision != c0->p.precision)
       return c0->fail(LBM_E_INVALID, "batch contexts must share device, dimension and precision");
     for (int j = 0; j < i; ++j)

@@ -44,7 +44,7 @@ class lbm_params(C.Structure):
         ("h0", C.c_double), ("p_exp", C.c_double),
         ("eps_n", C.c_double), ("eps_q", C.c_double), ("tie_eps", C.c_double),
         ("rep_orient", C.c_int), ("dispersed", C.c_int), ("cac_compress", C.c_int),
-        ("diag_interval", C.c_int), ("pstar_ref", C.c_double),
+        ("diag_interval", C.c_int), ("pstar_ref", C.c_double), ("cac_solver", C.c_int),
     ]
 
 
@@ -127,6 +127,7 @@ def to_c_params(p: Params) -> lbm_params:
     s.rep_orient, s.dispersed, s.cac_compress = p.rep_orient, p.dispersed, p.cac_compress
     s.diag_interval = p.diag_interval
     s.pstar_ref = getattr(p, "pstar_ref", 0.0)
+    s.cac_solver = getattr(p, "cac_solver", 0)
     return s
 
 
@@ -292,11 +293,11 @@ class Lattice:
 
     def kernel_times(self):
         """{kernel: (total_ms, launches)} since the last call (synchronises)."""
-        ms = np.zeros(4)
-        cnt = (C.c_long * 4)()
+        ms = np.zeros(5)
+        cnt = (C.c_long * 5)()
         self._check(self.lib.lbm_kernel_times(self.h, _dp(ms), cnt))
-        names = ("phi", "nci", "collide", "diag")
-        return {names[k]: (float(ms[k]), int(cnt[k])) for k in range(4)}
+        names = ("phi", "nci", "collide", "diag", "muscl")
+        return {names[k]: (float(ms[k]), int(cnt[k])) for k in range(5)}
 
     def save_state(self) -> bytes:
         n = int(self.lib.lbm_state_bytes(self.h))

@@ -36,10 +36,14 @@ def test_workspace_bytes_model():
     assert b - b16 >= 2 * n * 19 * 0.99
     p64 = p.replace(precision="fp64")
     assert L.lbm_workspace_bytes(p64) > 1.9 * b
+    # the finite-difference phase field adds a second phi plane and the u, a planes
+    bfd = L.lbm_workspace_bytes(p.replace(cac_solver=1))
+    assert 4 * n * (1 + 6) <= bfd - b < 4 * n * (1 + 6) * 1.02
 
 
 @pytest.mark.parametrize("bad", [dict(dim=4), dict(nx=0), dict(tau=0.5), dict(nci_window=5),
-                                 dict(eps_q=0.2), dict(rep_orient=2), dict(precision="fp8")])
+                                 dict(eps_q=0.2), dict(rep_orient=2), dict(precision="fp8"),
+                                 dict(cac_solver=2)])
 def test_invalid_params_rejected(bad):
     kw = dict(dim=2, nx=32, ny=32, nz=1)
     kw.update(bad)
