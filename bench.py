@@ -40,6 +40,12 @@ COLLIDE_BYTES = {("fp32", 3): 212, ("fp16", 3): 136, ("bf16", 3): 136, ("fp64", 
 # Whole coupled step (phi moment reads g and writes phi; collide as above):
 STEP_BYTES = {("fp32", 3): 212 + 28 + 4, ("fp16", 3): 136 + 28 + 4, ("bf16", 3): 136 + 28 + 4,
               ("fp64", 3): 424 + 56 + 8}
+# With the finite-difference phase field (Sec. 2.1.1) the collide moves f, reads
+# phi and writes u and a = phi (1 - phi) n (2 dim reals); the flag pass reads
+# phi; the update reads phi, u and a once each and writes phi.
+#   FP32 3D: collide 152 + 4 + 24 = 180 B; step 180 + 4 + (4 + 24 + 4) = 216 B.
+COLLIDE_BYTES_FD = {("fp32", 3): 180, ("fp16", 3): 104, ("bf16", 3): 104, ("fp64", 3): 360}
+STEP_BYTES_FD = {("fp32", 3): 216, ("fp16", 3): 140, ("bf16", 3): 140, ("fp64", 3): 432}
 
 
 def kernel_hash() -> str:
@@ -47,8 +53,9 @@ def kernel_hash() -> str:
 
 
 def workload_key(args) -> str:
-    return (f"{args.workload} n={args.n} bubbles={args.bubbles} r={args.rmin:g}-{args.rmax:g} "
-            f"gap={args.gap:g} {args.precision}")
+    key = (f"{args.workload} n={args.n} bubbles={args.bubbles} r={args.rmin:g}-{args.rmax:g} "
+           f"gap={args.gap:g} {args.precision}")
+    return key + (" muscl" if args.phase_field == "muscl" else "")
 
 
 def traffic_from_profile(args):
@@ -79,7 +86,9 @@ def make_workload(args):
     else:
         st = W.config_collision_3d(precision=args.precision)
         desc = f"droplet collision 256x128x128, D3Q19+D3Q7, {args.precision}"
-    st.params = st.params.replace(diag_interval=args.diag)
+    st.params = st.params.replace(diag_interval=args.diag, cac_solver=1 if args.phase_field == "muscl" else 0)
+    if args.phase_field == "muscl":
+        desc += ", finite-difference MUSCL-TVD phase field"
     return st, desc
 
 
@@ -91,7 +100,8 @@ def cpu_baseline(args):
     n = args.cpu_n
     bubbles = max(1, int(round(args.bubbles * (n / args.n) ** 3)))
     st = W.config_swarm(n=n, bubbles=bubbles, rmin=args.rmin, rmax=args.rmax, gap=args.gap, precision="fp64")
-    o = Oracle(st.params)
+    fd = args.phase_field == "muscl"
+    o = Oracle(st.params.replace(cac_solver=1 if fd else 0))
     o.init_fields(st.phi, st.u)
     o.step(1)
     t0 = time.perf_counter()
@@ -100,8 +110,8 @@ def cpu_baseline(args):
     mlups = n ** 3 * args.cpu_steps / dt / 1e6
     return {"value": round(mlups, 3), "unit": "MLUPS", "cores": o.lib.oracle_threads(),
             "kind": "oracle",
-            "sample": f"swarm recipe on {n}^3 ({bubbles} bubbles), FP64 oracle, {args.cpu_steps} steps, "
-                      f"{dt:.1f} s"}
+            "sample": f"swarm recipe on {n}^3 ({bubbles} bubbles), FP64 oracle"
+                      f"{' (MUSCL phase field)' if fd else ''}, {args.cpu_steps} steps, {dt:.1f} s"}
 
 
 def serving_report(args):
@@ -137,6 +147,9 @@ def main():
     ap.add_argument("--gap", type=float, default=3.0)
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp16", "bf16", "fp64"])
     ap.add_argument("--diag", type=int, default=100)
+    ap.add_argument("--phase-field", default="lbm", choices=["lbm", "muscl"],
+                    help="phase-field solver: lattice Boltzmann (Sec. 2.1.2) or finite-difference MUSCL-TVD "
+                         "(Sec. 2.1.1)")
     ap.add_argument("--cpu-n", type=int, default=96)
     ap.add_argument("--cpu-steps", type=int, default=60)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -222,7 +235,9 @@ def main():
     tiles = gated.reshape(p.nz // t, t, p.ny // 8, 8, p.nx // 8, 8).any(axis=(1, 3, 5)).sum()
     tile_cells = int(tiles) * 8 * 8 * t
     real = 8 if p.precision == "fp64" else 4
-    bytes_launch = COLLIDE_BYTES[(p.precision, p.dim)] * N + p.dim * real * tile_cells
+    fd = p.cac_solver != 0
+    step_bytes = (STEP_BYTES_FD if fd else STEP_BYTES).get((p.precision, p.dim))
+    bytes_launch = (COLLIDE_BYTES_FD if fd else COLLIDE_BYTES)[(p.precision, p.dim)] * N + p.dim * real * tile_cells
     coll_ms, coll_n = kt["collide"]
     avg_s = coll_ms / coll_n / 1e3
     achieved = bytes_launch / avg_s / 1e9
@@ -247,9 +262,8 @@ def main():
                      "traffic": traffic, "kernel": "k_collide (fused collide+stream)",
                      "bytes_per_launch": bytes_launch,
                      "avg_launch_ms": round(avg_s * 1e3, 4),
-                     "step_model_bytes_per_cell": STEP_BYTES.get((p.precision, p.dim)),
-                     "step_frac": round(STEP_BYTES.get((p.precision, p.dim), 0) * N / (ms_step / 1e3) / 1e9
-                                        / PEAK_HBM_GBS, 4)},
+                     "step_model_bytes_per_cell": step_bytes,
+                     "step_frac": round((step_bytes or 0) * N / (ms_step / 1e3) / 1e9 / PEAK_HBM_GBS, 4)},
         "kernel_ms_per_launch": {k: round(v[0] / max(v[1], 1), 4) for k, v in kt.items()},
         "copy_gbs": round(copy_gbs, 1),
         "state": {"step": diag["step"], "n_bubbles": diag["n_droplets"], "nci_active": diag["nci_active"],
