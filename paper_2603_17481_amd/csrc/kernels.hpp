@@ -1083,13 +1083,10 @@ __device__ __forceinline__ int wrap2(int v, int n) {
   return v;
 }
 
-// Eq. minmod: the smaller slope when both have the same sign, else zero.
-template <typename T>
-__device__ __forceinline__ T minmod(T a, T b) {
-  if (a * b <= (T)0) return (T)0;
-  const T m = fabs(a) < fabs(b) ? fabs(a) : fabs(b);
-  return a > (T)0 ? m : -m;
-}
+// Eq. minmod: the smaller slope when both have the same sign, else zero, i.e.
+// the median of (0, a, b) (one v_med3 in FP32).
+__device__ __forceinline__ float minmod(float a, float b) { return __builtin_amdgcn_fmed3f(0.0f, a, b); }
+__device__ __forceinline__ double minmod(double a, double b) { return fmax(fmin(a, b), fmin(fmax(a, b), 0.0)); }
 
 // Advective flux through the face between cells 0 and 1 (Eqs. face_flux_def,
 // slope_minmod_x, recon_lr_x, upwind_select_x): phi reconstructed linearly
@@ -1097,66 +1094,262 @@ __device__ __forceinline__ T minmod(T a, T b) {
 // cells 0 and 1) and taken from the upwind side of the face velocity uf.
 template <typename T>
 __device__ __forceinline__ T face_flux(T pm, T p0, T p1, T p2, T uf) {
-  const T phL = p0 + (T)0.5 * minmod(p0 - pm, p1 - p0);
-  const T phR = p1 - (T)0.5 * minmod(p1 - p0, p2 - p1);
+  const T d = p1 - p0;
+  const T phL = fmad((T)0.5, minmod(p0 - pm, d), p0);
+  const T phR = fmad((T)-0.5, minmod(d, p2 - p1), p1);
   return uf * (uf >= (T)0 ? phL : phR);
 }
 
-// phi' = phi - div_h(u phi) + M lap_h phi - kappa div_iso(a), every term from
-// the state before the step: u the velocity of that state's collision, the
-// face velocity the mean of the two cells', lap_h the isotropic Laplacian
+// F(x + e_ax / 2) - F(x - e_ax / 2) of the advective flux along axis ax.
+// Accessors: ph(dx, dy, dz) phi at an offset of up to two cells along ax,
+// uv(ax, d) velocity component ax at offset d along ax.
+template <typename T, typename PH, typename UV>
+__device__ __forceinline__ T flux_difference(const PH& ph, const UV& uv, int ax) {
+  T p[5];
+#pragma unroll
+  for (int k = 0; k < 5; ++k) p[k] = ph(ax == 0 ? k - 2 : 0, ax == 1 ? k - 2 : 0, ax == 2 ? k - 2 : 0);
+  const T um = uv(ax, -1), u0 = uv(ax, 0), up = uv(ax, 1);
+  const T fp = face_flux(p[1], p[2], p[3], p[4], (T)0.5 * (u0 + up));
+  const T fm = face_flux(p[0], p[1], p[2], p[3], (T)0.5 * (um + u0));
+  return fp - fm;
+}
+
+// Increment phi' - phi = -div_h(u phi) + M lap_h phi - kappa div_iso(a), every
+// term from the state before the step (div = div_h(u phi), the sum of the
+// flux differences over the axes): u the velocity of that state's collision,
+// the face velocity the mean of the two cells', lap_h the isotropic Laplacian
 // (Eq. lap_iso), a = phi (1 - phi) n written by the collision, div_iso(a) =
 // (1/cs^2) sum_i w_i c_i . a(x + c_i) on the hydrodynamic lattice and kappa =
-// 4 M / W (Eqs. source_sharp, kappa_delta).  ua holds u (DIM planes) then a
-// (DIM planes), plane stride S; out must not alias phi.
+// 4 M / W (Eqs. source_sharp, kappa_delta).  Accessors: ph(dx, dy, dz) phi at
+// a lattice offset, av(comp, dx, dy, dz) component comp of a at one.
+// Both stencils are summed per weight class (|c|^2 = 1, 2) before the weight
+// is applied.  The Laplacian is summed over differences to the cell, so that
+// it vanishes exactly on a uniform field (the rounded weights sum to one only
+// approximately, and that residue would add mass every step), and the
+// increment is formed before it is added to phi (added term by term, parts
+// smaller than half an ulp of phi would each be rounded away).
+template <int DIM, typename T, typename PH, typename AV>
+__device__ __forceinline__ T muscl_increment(const PH& ph, const AV& av, T div, T mob, T kap) {
+  using H = Hydro<DIM>;
+  const T pc = ph(0, 0, 0);
+  T sl[2] = {0, 0}, dc[2] = {0, 0};
+#pragma unroll
+  for (int i = 1; i < H::Q; i += 2) {
+    const int c[3] = {H::cx[i], H::cy[i], H::cz[i]};
+    const int cl = c[0] * c[0] + c[1] * c[1] + c[2] * c[2] - 1;
+    sl[cl] += (ph(c[0], c[1], c[2]) - pc) + (ph(-c[0], -c[1], -c[2]) - pc);
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+      if (!c[a]) continue;
+      const T d = av(a, c[0], c[1], c[2]) - av(a, -c[0], -c[1], -c[2]);
+      dc[cl] += c[a] > 0 ? d : -d;
+    }
+  }
+  const T w1 = wt<H, T>(1), w2 = wt<H, T>(H::Q - 1);
+  const T lap = (T)6 * (w1 * sl[0] + w2 * sl[1]);
+  const T dvi = (T)3 * (w1 * dc[0] + w2 * dc[1]);
+  return (mob * lap - div) - kap * dvi;
+}
+
+// One cell per thread, neighbours read from global memory (2D boxes).  ua holds
+// u (DIM planes) then a (DIM planes), plane stride S; out must not alias phi.
 template <int DIM, typename T>
 __global__ __launch_bounds__(NT) void k_muscl(const T* __restrict__ phi, T* __restrict__ out,
                                               const T* __restrict__ ua, Geo geo, T mob, T kap) {
-  using H = Hydro<DIM>;
   int x, y, z;
   block_cell(swizzled_block(), geo, x, y, z);
   if (x >= geo.nx || y >= geo.ny) return;
   const long long S = geo.S;
-  const Nbr nb(x, y, z, geo);
-  const int idx = nb(0, 0, 0);
   const int cc[3] = {x, y, z};
   const int nn[3] = {geo.nx, geo.ny, geo.nz};
   const int st[3] = {1, geo.nx, geo.nx * geo.ny};
+  const int idx = x + geo.nx * (y + geo.ny * z);
+  // offset of the cell d cells along axis ax (|d| <= 2, periodic)
+  auto at = [&](int ax, int d) { return (wrap2(cc[ax] + d, nn[ax]) - cc[ax]) * st[ax]; };
+  auto off = [&](int dx, int dy, int dz) {
+    int o = idx;
+    if (dx) o += at(0, dx);
+    if (dy) o += at(1, dy);
+    if (DIM == 3 && dz) o += at(2, dz);
+    return o;
+  };
+  const T* A = ua + DIM * S;
+  auto ph = [&](int dx, int dy, int dz) { return phi[off(dx, dy, dz)]; };
+  auto uv = [&](int ax, int d) { return ua[ax * S + (d ? idx + at(ax, d) : idx)]; };
   T div = 0;
 #pragma unroll
-  for (int ax = 0; ax < DIM; ++ax) {
-    int o[5];
+  for (int ax = 0; ax < DIM; ++ax) div += flux_difference<T>(ph, uv, ax);
+  const T inc = muscl_increment<DIM, T>(
+      ph, [&](int a, int dx, int dy, int dz) { return A[a * S + off(dx, dy, dz)]; }, div, mob, kap);
+  out[idx] = phi[idx] + inc;
+}
+
+// 3D: a block owns a 64 x TY column of cells and marches along z through
+// MUSCL_ZRUN planes.  Each plane of phi (halo 2) and of a (halo 1) is fetched
+// from HBM once per block into an LDS ring of three planes (z-1, z, z+1), u_x
+// and u_y of plane z likewise; the cell's own phi at z +- 2 and u_z at z +- 1
+// stay in registers.  Every neighbour read of the update then comes from LDS
+// or registers (about ten global loads per cell instead of about seventy), and
+// the loads of the next plane are issued before the update of this one, so
+// that their latency hides behind its arithmetic.
+#ifndef MUSCL_ZRUN
+#define MUSCL_ZRUN 64
+#endif
+#ifndef MUSCL_TY32
+#define MUSCL_TY32 4
+#endif
+constexpr int MZ_TX = 64;
+template <typename T>
+struct MuslTile {
+  static constexpr int TY = sizeof(T) == 8 ? 4 : MUSCL_TY32;   // rows per block
+  static constexpr int NT = MZ_TX * TY;
+  static constexpr int PW = MZ_TX + 4, PN = PW * (TY + 4);   // phi planes, halo 2
+  static constexpr int AW = MZ_TX + 2, AN = AW * (TY + 2);   // a and u planes, halo 1
+  static constexpr int KP = (PN + NT - 1) / NT, KA = (AN + NT - 1) / NT;   // staged cells per thread
+};
+
+template <typename T>
+__global__ __launch_bounds__(MuslTile<T>::NT) void k_muscl3(const T* __restrict__ phi, T* __restrict__ out,
+                                                            const T* __restrict__ ua, Geo geo, T mob, T kap,
+                                                            int ntx, int nty) {
+  using M = MuslTile<T>;
+  constexpr int KP = M::KP, KA = M::KA;
+  __shared__ T sp[3][M::PN];
+  __shared__ T sa[3][3][M::AN];
+  __shared__ T su[2][M::AN];
+  const int t = swizzled_block();
+  const int tx = t % ntx, r = t / ntx, ty = r % nty, zc = r / nty;
+  const int x0 = tx * MZ_TX, y0 = ty * M::TY;
+  const int z0 = zc * MUSCL_ZRUN, z1 = min(z0 + MUSCL_ZRUN, geo.nz);
+  const int tid = threadIdx.x, lx = tid & (MZ_TX - 1), ly = tid / MZ_TX;
+  const int nx = geo.nx, ny = geo.ny, nz = geo.nz;
+  const bool valid = x0 + lx < nx && y0 + ly < ny;
+  const int plane = nx * ny;
+  const int own = valid ? (x0 + lx) + nx * (y0 + ly) : 0;
+  const long long S = geo.S;
+  // in-plane byte offsets of the staged halo cells, the same on every plane;
+  // the slots k below NT-multiples of the plane size are always in use
+  unsigned po[KP], ao[KA];
+  auto usedp = [&](int k) { return (k + 1) * M::NT <= M::PN || tid + k * M::NT < M::PN; };
+  auto useda = [&](int k) { return (k + 1) * M::NT <= M::AN || tid + k * M::NT < M::AN; };
 #pragma unroll
-    for (int k = 0; k < 5; ++k) o[k] = idx + (wrap2(cc[ax] + k - 2, nn[ax]) - cc[ax]) * st[ax];
-    const T p0 = phi[o[0]], p1 = phi[o[1]], p2 = phi[o[2]], p3 = phi[o[3]], p4 = phi[o[4]];
-    const T* U = ua + ax * S;
-    const T um = U[o[1]], u0 = U[o[2]], up = U[o[3]];
-    const T fp = face_flux(p1, p2, p3, p4, (T)0.5 * (u0 + up));
-    const T fm = face_flux(p0, p1, p2, p3, (T)0.5 * (um + u0));
-    div += fp - fm;
+  for (int k = 0; k < KP; ++k) {
+    const int s = tid + k * M::NT;
+    po[k] = usedp(k) ? (unsigned)(wrapi(x0 - 2 + s % M::PW, nx) + nx * wrapi(y0 - 2 + s / M::PW, ny)) * sizeof(T)
+                     : 0u;
   }
-  // Laplacian summed over differences to the cell (Eq. lap_iso), so that it
-  // vanishes exactly on a uniform field: the rounded weights sum to one only
-  // approximately, and that residue would otherwise add mass every step.
-  const T* A = ua + DIM * S;
-  const T pc = phi[idx];
-  T sl = 0, dc = 0;
 #pragma unroll
-  for (int i = 1; i < H::Q; i += 2) {
-    const int c[3] = {H::cx[i], H::cy[i], H::cz[i]};
-    const int yp = nb(c[0], c[1], c[2]), ym = nb(-c[0], -c[1], -c[2]);
-    const T w = wt<H, T>(i);
-    sl += w * ((phi[yp] - pc) + (phi[ym] - pc));
+  for (int k = 0; k < KA; ++k) {
+    const int s = tid + k * M::NT;
+    ao[k] = useda(k) ? (unsigned)(wrapi(x0 - 1 + s % M::AW, nx) + nx * wrapi(y0 - 1 + s / M::AW, ny)) * sizeof(T)
+                     : 0u;
+  }
+  const unsigned owno = (unsigned)own * sizeof(T);
+  // a plane of a field as a uniform base; cells are read at 32-bit byte offsets
+  auto zbase = [&](const T* f, int z) { return (const char*)(f + (long long)wrapi(z, nz) * plane); };
+  auto ld = [](const char* b, unsigned o) { return *(const T*)(b + o); };
+  const T* A = ua + 3 * S;
+  // registers in flight: phi and a of plane zr + 1, u_x and u_y of plane zr,
+  // own phi at zr + 2 and u_z at zr + 1
+  T rp[KP], ra[3][KA], ru[2][KA], rq = 0, rv = 0;
+  auto fetch = [&](int zr) {
+    const char* bp = zbase(phi, zr + 1);
 #pragma unroll
-    for (int a = 0; a < DIM; ++a) {
-      if (!c[a]) continue;
-      const T d = w * (A[a * S + yp] - A[a * S + ym]);
-      dc += c[a] > 0 ? d : -d;
+    for (int k = 0; k < KP; ++k) rp[k] = usedp(k) ? ld(bp, po[k]) : (T)0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const char* ba = zbase(A + a * S, zr + 1);
+#pragma unroll
+      for (int k = 0; k < KA; ++k) ra[a][k] = useda(k) ? ld(ba, ao[k]) : (T)0;
     }
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      const char* bu = zbase(ua + a * S, zr);
+#pragma unroll
+      for (int k = 0; k < KA; ++k) ru[a][k] = useda(k) ? ld(bu, ao[k]) : (T)0;
+    }
+    if (valid) {
+      rq = ld(zbase(phi, zr + 2), owno);
+      rv = ld(zbase(ua + 2 * S, zr + 1), owno);
+    }
+  };
+  auto put_p = [&](T* dst, const T* v) {
+#pragma unroll
+    for (int k = 0; k < KP; ++k)
+      if (usedp(k)) dst[tid + k * M::NT] = v[k];
+  };
+  auto put_a = [&](T* dst, const T* v) {
+#pragma unroll
+    for (int k = 0; k < KA; ++k)
+      if (useda(k)) dst[tid + k * M::NT] = v[k];
+  };
+  // prologue: planes z0 - 1 and z0 into ring slots 0 and 1, own column registers
+  int sm = 0, s0 = 1, sq = 2;
+  for (int d = -2; d <= -1; ++d) {
+    fetch(z0 + d);
+    put_p(sp[d + 2], rp);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) put_a(sa[d + 2][a], ra[a]);
   }
-  // The increment is formed first and added once: added term by term, the
-  // parts smaller than half an ulp of phi would each be rounded away.
-  out[idx] = pc + ((mob * ((T)6 * sl) - div) - kap * ((T)3 * dc));
+  T q0 = 0, q1 = 0, q2 = 0, q3 = 0, v0 = 0, v1 = 0;
+  if (valid) {
+    q0 = ld(zbase(phi, z0 - 2), owno);
+    q1 = ld(zbase(phi, z0 - 1), owno);
+    q2 = ld(zbase(phi, z0), owno);
+    q3 = ld(zbase(phi, z0 + 1), owno);
+    v0 = ld(zbase(ua + 2 * S, z0 - 1), owno);
+    v1 = ld(zbase(ua + 2 * S, z0), owno);
+  }
+  fetch(z0);
+  T fzm = face_flux(q0, q1, q2, q3, (T)0.5 * (v0 + v1));   // flux through the face z0 - 1/2
+  const int cp = (ly + 2) * M::PW + lx + 2;   // the cell in a phi plane
+  const int ca = (ly + 1) * M::AW + lx + 1;   // the cell in an a / u plane
+  for (int z = z0; z < z1; ++z) {
+    put_p(sp[sq], rp);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) put_a(sa[sq][a], ra[a]);
+    put_a(su[0], ru[0]);
+    put_a(su[1], ru[1]);
+    const T q4 = rq, v2 = rv;
+    __syncthreads();
+    if (z + 1 < z1) fetch(z + 1);
+    if (valid) {
+      const T* Pm = sp[sm];
+      const T* P0 = sp[s0];
+      const T* Pp = sp[sq];
+      auto ph = [&](int dx, int dy, int dz) -> T {
+        if (dz == -2) return q0;
+        if (dz == 2) return q4;
+        const T* P = dz < 0 ? Pm : (dz > 0 ? Pp : P0);
+        return P[cp + dy * M::PW + dx];
+      };
+      auto uv = [&](int ax, int d) -> T {
+        if (ax == 2) return d < 0 ? v0 : (d > 0 ? v2 : v1);
+        return su[ax][ca + (ax == 0 ? d : d * M::AW)];
+      };
+      auto av = [&](int a, int dx, int dy, int dz) -> T {
+        const int sl = dz < 0 ? sm : (dz > 0 ? sq : s0);
+        return sa[sl][a][ca + dy * M::AW + dx];
+      };
+      // the face below this cell is the face above the previous one
+      const T fzp = face_flux(q1, q2, q3, q4, (T)0.5 * (v1 + v2));
+      const T div = (flux_difference<T>(ph, uv, 0) + flux_difference<T>(ph, uv, 1)) + (fzp - fzm);
+      fzm = fzp;
+      const T inc = muscl_increment<3, T>(ph, av, div, mob, kap);
+      *(T*)((char*)(out + (long long)z * plane) + owno) = q2 + inc;
+    }
+    __syncthreads();
+    const int tmp = sm;
+    sm = s0;
+    s0 = sq;
+    sq = tmp;
+    q0 = q1;
+    q1 = q2;
+    q2 = q3;
+    q3 = q4;
+    v0 = v1;
+    v1 = v2;
+  }
 }
 
 // ---------------------------------------------------------------------------

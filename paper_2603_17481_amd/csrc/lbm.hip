@@ -396,8 +396,17 @@ struct Engine {
     const double kap = c->p.cac_compress ? 4.0 * c->p.mobility / c->p.width : 0.0;
     {
       Timed tm(c, 4);
-      hipLaunchKernelGGL((k_muscl<DIM, T>), rows(c), dim3(NT), 0, c->stream, (const T*)c->phi(),
-                         (T*)c->phi_next(), (const T*)c->ua(), c->geo, (T)c->p.mobility, (T)kap);
+      if constexpr (DIM == 3) {
+        using M = MuslTile<T>;
+        const int ntx = (c->p.nx + MZ_TX - 1) / MZ_TX, nty = (c->p.ny + M::TY - 1) / M::TY;
+        const int nzc = (c->p.nz + MUSCL_ZRUN - 1) / MUSCL_ZRUN;
+        hipLaunchKernelGGL((k_muscl3<T>), dim3((unsigned)(ntx * nty * nzc)), dim3(M::NT), 0, c->stream,
+                           (const T*)c->phi(), (T*)c->phi_next(), (const T*)c->ua(), c->geo,
+                           (T)c->p.mobility, (T)kap, ntx, nty);
+      } else {
+        hipLaunchKernelGGL((k_muscl<DIM, T>), rows(c), dim3(NT), 0, c->stream, (const T*)c->phi(),
+                           (T*)c->phi_next(), (const T*)c->ua(), c->geo, (T)c->p.mobility, (T)kap);
+      }
     }
     c->phi_cur ^= 1;
   }
