@@ -29,7 +29,8 @@ if ROOT not in sys.path:
 PEAK_HBM_GBS = 8000.0
 METRIC = "MLUPS + % of HBM roofline per coupled step; served jobs/s + p99 latency"
 KERNEL_SRC = os.path.join(ROOT, "paper_2603_17481_amd", "csrc", "kernels.hpp")
-COUNTERS = os.path.join(ROOT, "profiles", "collide_swarm512_fp32_counters.md")
+COUNTERS = [os.path.join(ROOT, "profiles", f) for f in
+            ("collide_swarm512_fp32_counters.md", "kernels_swarm512_fp32_muscl.md")]
 
 # Algorithmic bytes per cell of the fused collide+stream kernel (each population
 # read once and written once, phi read once; J read only in near-contact tiles):
@@ -59,20 +60,20 @@ def workload_key(args) -> str:
 
 
 def traffic_from_profile(args):
-    """HBM bytes per step of the collide kernel from the committed rocprofv3
-    counter summary, or None when it is missing, was taken on another workload
-    or on another version of the kernels."""
-    if not os.path.exists(COUNTERS):
-        return None
-    txt = open(COUNTERS).read()
-    m_hash = re.search(r"kernel source sha256\[:16\]: ([0-9a-f]+)", txt)
-    m_key = re.search(r"workload key: (.+)", txt)
-    m_bytes = re.search(r"hbm bytes per launch: ([0-9.eE+]+)", txt)
-    if not m_hash or not m_bytes or not m_key or m_hash.group(1) != kernel_hash():
-        return None
-    if m_key.group(1).strip() != workload_key(args):
-        return None
-    return float(m_bytes.group(1))
+    """HBM bytes per launch of the collide kernel from a committed rocprofv3
+    counter summary of this workload and this version of the kernels, or None."""
+    for path in COUNTERS:
+        if not os.path.exists(path):
+            continue
+        txt = open(path).read()
+        m_hash = re.search(r"kernel source sha256\[:16\]: ([0-9a-f]+)", txt)
+        m_key = re.search(r"workload key: (.+)", txt)
+        m_bytes = re.search(r"hbm bytes per launch: ([0-9.eE+]+)", txt)
+        if not m_hash or not m_bytes or not m_key or m_hash.group(1) != kernel_hash():
+            continue
+        if m_key.group(1).strip() == workload_key(args):
+            return float(m_bytes.group(1))
+    return None
 
 
 def make_workload(args):
