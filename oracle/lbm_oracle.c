@@ -87,6 +87,25 @@ static void make_d3q19(lattice* L) {
   finish_lattice(L);
 }
 
+/* D3Q27 (the paper's hydrodynamic lattice): rest 8/27, axis 2/27, face diagonal
+ * 1/54, body diagonal 1/216, cs^2 = 1/3 */
+static void make_d3q27(lattice* L) {
+  int k = 0;
+  L->q = 27;
+  L->cs2 = 1.0 / 3.0;
+  for (int z = -1; z <= 1; ++z)
+    for (int y = -1; y <= 1; ++y)
+      for (int x = -1; x <= 1; ++x) {
+        int s = abs(x) + abs(y) + abs(z);
+        L->c[k][0] = x;
+        L->c[k][1] = y;
+        L->c[k][2] = z;
+        L->w[k] = s == 0 ? 8.0 / 27.0 : (s == 1 ? 2.0 / 27.0 : (s == 2 ? 1.0 / 54.0 : 1.0 / 216.0));
+        ++k;
+      }
+  finish_lattice(L);
+}
+
 /* D3Q7 (phase field): rest 1/4, axis 1/8, cs^2 = 1/4 */
 static void make_d3q7(lattice* L) {
   int k = 0;
@@ -111,6 +130,7 @@ int oracle_lattice(int kind, int* q, int* c, double* w, double* cs2) {
   if (kind == 0) make_d2q9(&L);
   else if (kind == 1) make_d3q19(&L);
   else if (kind == 2) make_d3q7(&L);
+  else if (kind == 3) make_d3q27(&L);
   else return -1;
   *q = L.q;
   *cs2 = L.cs2;
@@ -184,28 +204,32 @@ static void regularize(const lattice* L, int D, const double* fneq, const double
   }
 }
 
-static void hydro_lattice(int dim, lattice* L) {
+/* Hydrodynamic lattice: D2Q9 in 2D; D3Q19 (q = 19, or 0) or D3Q27 (q = 27) in 3D. */
+static int hydro_lattice(int dim, int q, lattice* L) {
   if (dim == 2) make_d2q9(L);
-  else make_d3q19(L);
+  else if (q == 27) make_d3q27(L);
+  else if (q == 19 || q == 0) make_d3q19(L);
+  else return -1;
+  return 0;
 }
 
-int oracle_feq(int dim, double pstar, const double* u, double* out) {
+int oracle_feq(int dim, int q, double pstar, const double* u, double* out) {
   lattice L;
-  hydro_lattice(dim, &L);
+  if (hydro_lattice(dim, q, &L)) return -1;
   for (int i = 0; i < L.q; ++i) out[i] = feq_i(&L, dim, i, pstar, u);
   return 0;
 }
 
-int oracle_guo(int dim, const double* u, const double* F, double rho, double* out) {
+int oracle_guo(int dim, int q, const double* u, const double* F, double rho, double* out) {
   lattice L;
-  hydro_lattice(dim, &L);
+  if (hydro_lattice(dim, q, &L)) return -1;
   for (int i = 0; i < L.q; ++i) out[i] = guo_i(&L, dim, i, u, F, rho);
   return 0;
 }
 
-int oracle_regularize(int dim, const double* fneq, const double* u, double* out) {
+int oracle_regularize(int dim, int q, const double* fneq, const double* u, double* out) {
   lattice L;
-  hydro_lattice(dim, &L);
+  if (hydro_lattice(dim, q, &L)) return -1;
   regularize(&L, dim, fneq, u, out);
   return 0;
 }
@@ -364,6 +388,7 @@ static double* dalloc(long n) { return (double*)calloc((size_t)n, sizeof(double)
 oracle_state* oracle_create(const oracle_params* p) {
   if (!p || (p->dim != 2 && p->dim != 3) || p->nx < 1 || p->ny < 1 || (p->dim == 3 && p->nz < 1))
     return NULL;
+  if (p->dim == 3 && p->hydro_q != 0 && p->hydro_q != 19 && p->hydro_q != 27) return NULL;
   oracle_state* s = (oracle_state*)calloc(1, sizeof(oracle_state));
   s->P = *p;
   s->D = p->dim;
@@ -376,7 +401,7 @@ oracle_state* oracle_create(const oracle_params* p) {
     make_d2q9(&s->LF);
     make_d2q9(&s->LG);
   } else {
-    make_d3q19(&s->LF);
+    hydro_lattice(3, p->hydro_q, &s->LF);
     make_d3q7(&s->LG);
   }
   long N = s->N;

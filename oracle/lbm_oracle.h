@@ -36,6 +36,7 @@ typedef struct {
   int cac_solver;          /* phase field: 0 conservative Allen-Cahn lattice Boltzmann
                               (g populations); 1 finite-difference MUSCL-TVD update of
                               phi (Sec. 2.1.1, Eq. phi_update_muscl)                   */
+  int hydro_q;             /* 3D hydrodynamic lattice: 19 (or 0) D3Q19, 27 D3Q27      */
   int store_round;         /* test knob: 0 none; round stored populations after each
                               step to 1 float32, 2 half (f), 3 bfloat16 (f)            */
 } oracle_params;
@@ -54,7 +55,7 @@ typedef struct {
 
 typedef struct oracle_state oracle_state;
 
-/* Lattice tables: kind 0 = D2Q9, 1 = D3Q19, 2 = D3Q7.  c is q x 3 ints, w is q doubles. */
+/* Lattice tables: kind 0 = D2Q9, 1 = D3Q19, 2 = D3Q7, 3 = D3Q27.  c is q x 3 ints, w is q doubles. */
 int oracle_lattice(int kind, int* q, int* c, double* w, double* cs2);
 
 oracle_state* oracle_create(const oracle_params* p);
@@ -85,9 +86,9 @@ int oracle_diagnostics(oracle_state* s, oracle_diag* out);
 int oracle_nci_from_qn(const oracle_params* p, const double* q, const double* n,
                        int* chi, int* partner, double* J);
 /* Third-order equilibrium, Guo source and regularised non-equilibrium of one cell (section 2.1). */
-int oracle_feq(int dim, double pstar, const double* u, double* out);
-int oracle_guo(int dim, const double* u, const double* F, double rho, double* out);
-int oracle_regularize(int dim, const double* fneq, const double* u, double* out);
+int oracle_feq(int dim, int q, double pstar, const double* u, double* out);
+int oracle_guo(int dim, int q, const double* u, const double* F, double rho, double* out);
+int oracle_regularize(int dim, int q, const double* fneq, const double* u, double* out);
 /* Film-thickness map and thickness weight of section 2.3.3 for one paired indicator. */
 double oracle_film_thickness(const oracle_params* p, double q_pair);
 double oracle_thickness_weight(const oracle_params* p, double h);

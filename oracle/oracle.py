@@ -26,7 +26,7 @@ class _Params(C.Structure):
         ("p_exp", C.c_double), ("eps_n", C.c_double), ("eps_q", C.c_double),
         ("tie_eps", C.c_double),
         ("rep_orient", C.c_int), ("dispersed", C.c_int), ("cac_compress", C.c_int),
-        ("cac_solver", C.c_int), ("store_round", C.c_int),
+        ("cac_solver", C.c_int), ("hydro_q", C.c_int), ("store_round", C.c_int),
     ]
 
 
@@ -72,9 +72,9 @@ def load():
     lib.oracle_get_gradients.argtypes = [vp, dp, dp, dp, dp, dp]
     lib.oracle_diagnostics.argtypes = [vp, C.POINTER(_Diag)]
     lib.oracle_nci_from_qn.argtypes = [C.POINTER(_Params), dp, dp, ip, ip, dp]
-    lib.oracle_feq.argtypes = [C.c_int, C.c_double, dp, dp]
-    lib.oracle_guo.argtypes = [C.c_int, dp, dp, C.c_double, dp]
-    lib.oracle_regularize.argtypes = [C.c_int, dp, dp, dp]
+    lib.oracle_feq.argtypes = [C.c_int, C.c_int, C.c_double, dp, dp]
+    lib.oracle_guo.argtypes = [C.c_int, C.c_int, dp, dp, C.c_double, dp]
+    lib.oracle_regularize.argtypes = [C.c_int, C.c_int, dp, dp, dp]
     lib.oracle_film_thickness.restype = C.c_double
     lib.oracle_film_thickness.argtypes = [C.POINTER(_Params), C.c_double]
     lib.oracle_thickness_weight.restype = C.c_double
@@ -112,12 +112,13 @@ def make_params(p, store_round: int = 0) -> _Params:
     s.tie_eps = p.tie_eps
     s.rep_orient, s.dispersed, s.cac_compress = p.rep_orient, p.dispersed, p.cac_compress
     s.cac_solver = p.cac_solver
+    s.hydro_q = getattr(p, "hydro_q", 19) if p.dim == 3 else 9
     s.store_round = int(store_round)
     return s
 
 
 def lattice(kind: int):
-    """kind 0 = D2Q9, 1 = D3Q19, 2 = D3Q7 -> (c[q,3] int, w[q], cs2)."""
+    """kind 0 = D2Q9, 1 = D3Q19, 2 = D3Q7, 3 = D3Q27 -> (c[q,3] int, w[q], cs2)."""
     lib = load()
     q = C.c_int()
     c = np.zeros(81, dtype=np.int32)
@@ -141,7 +142,7 @@ class Oracle:
             raise RuntimeError("oracle_create failed")
         self.N = params.n_cells
         self.dim = params.dim
-        self.qf = 9 if params.dim == 2 else 19
+        self.qf = 9 if params.dim == 2 else getattr(params, "hydro_q", 19)
         self.qg = 9 if params.dim == 2 else 7
 
     def close(self):
@@ -251,32 +252,40 @@ def nci_from_qn(params, q, n):
             J.reshape((params.dim,) + params.shape))
 
 
-def feq(dim, pstar, u):
+def _hydro_q(dim, q):
+    return 9 if dim == 2 else (q or 19)
+
+
+def feq(dim, pstar, u, q=None):
+    """Third-order equilibrium of one cell on D2Q9 (dim 2) or D3Q19 / D3Q27 (q)."""
     lib = load()
-    q = 9 if dim == 2 else 19
+    q = _hydro_q(dim, q)
     out = np.zeros(q)
     uu = np.ascontiguousarray(u, dtype=np.float64)
-    lib.oracle_feq(dim, float(pstar), _dptr(uu), _dptr(out))
+    if lib.oracle_feq(dim, q, float(pstar), _dptr(uu), _dptr(out)):
+        raise ValueError("unknown lattice")
     return out
 
 
-def guo(dim, u, F, rho):
+def guo(dim, u, F, rho, q=None):
     lib = load()
-    q = 9 if dim == 2 else 19
+    q = _hydro_q(dim, q)
     out = np.zeros(q)
     uu = np.ascontiguousarray(u, dtype=np.float64)
     FF = np.ascontiguousarray(F, dtype=np.float64)
-    lib.oracle_guo(dim, _dptr(uu), _dptr(FF), float(rho), _dptr(out))
+    if lib.oracle_guo(dim, q, _dptr(uu), _dptr(FF), float(rho), _dptr(out)):
+        raise ValueError("unknown lattice")
     return out
 
 
-def regularize(dim, fneq, u):
+def regularize(dim, fneq, u, q=None):
     lib = load()
-    q = 9 if dim == 2 else 19
+    q = _hydro_q(dim, q)
     out = np.zeros(q)
     a = np.ascontiguousarray(fneq, dtype=np.float64)
     uu = np.ascontiguousarray(u, dtype=np.float64)
-    lib.oracle_regularize(dim, _dptr(a), _dptr(uu), _dptr(out))
+    if lib.oracle_regularize(dim, q, _dptr(a), _dptr(uu), _dptr(out)):
+        raise ValueError("unknown lattice")
     return out
 
 

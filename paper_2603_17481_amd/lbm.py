@@ -170,7 +170,7 @@ class Lattice:
         self._cp = to_c_params(params)
         self.N = params.n_cells
         self.dim = params.dim
-        self.qf = 9 if params.dim == 2 else 19
+        self.qf = 9 if params.dim == 2 else params.hydro_q
         self.qg = 9 if params.dim == 2 else 7
         self._workspace = workspace     # keep the tensor alive
         ws_ptr, ws_bytes = None, 0
