@@ -32,21 +32,24 @@ KERNEL_SRC = os.path.join(ROOT, "paper_2603_17481_amd", "csrc", "kernels.hpp")
 COUNTERS = [os.path.join(ROOT, "profiles", f) for f in
             ("collide_swarm512_fp32_counters.md", "kernels_swarm512_fp32_muscl.md")]
 
-# Algorithmic bytes per cell of the fused collide+stream kernel (each population
-# read once and written once, phi read once; J read only in near-contact tiles):
-#   FP32: f 19*4*2 + g 7*4*2 + phi 4 = 212 B;  FP16/BF16 f: 19*2*2 + 56 + 4 = 136 B
-#   FP64: f 19*8*2 + g 7*8*2 + phi 8 = 424 B.  J: dim * sizeof(real) per tile cell.
-COLLIDE_BYTES = {("fp32", 3): 212, ("fp16", 3): 136, ("bf16", 3): 136, ("fp64", 3): 424,
-                 ("fp32", 2): 2 * 9 * 4 * 2 + 4, ("fp64", 2): 2 * 9 * 8 * 2 + 8}
-# Whole coupled step (phi moment reads g and writes phi; collide as above):
-STEP_BYTES = {("fp32", 3): 212 + 28 + 4, ("fp16", 3): 136 + 28 + 4, ("bf16", 3): 136 + 28 + 4,
-              ("fp64", 3): 424 + 56 + 8}
-# With the finite-difference phase field (Sec. 2.1.1) the collide moves f, reads
-# phi and writes u and a = phi (1 - phi) n (2 dim reals); the flag pass reads
-# phi; the update reads phi, u and a once each and writes phi.
-#   FP32 3D: collide 152 + 4 + 24 = 180 B; step 180 + 4 + (4 + 24 + 4) = 216 B.
-COLLIDE_BYTES_FD = {("fp32", 3): 180, ("fp16", 3): 104, ("bf16", 3): 104, ("fp64", 3): 360}
-STEP_BYTES_FD = {("fp32", 3): 216, ("fp16", 3): 140, ("bf16", 3): 140, ("fp64", 3): 432}
+# Algorithmic bytes per cell (each population read once and written once, phi
+# read once; J read only in near-contact tiles, added per tile cell).
+#   collide, lattice Boltzmann phase field: f 2 Q fs + g 2 QG rs + phi rs
+#     (3D FP32 D3Q19: 152 + 56 + 4 = 212 B; FP16 f: 76 + 56 + 4 = 136 B; D3Q27: 276 B)
+#   collide, finite-difference phase field (Sec. 2.1.1): f 2 Q fs + phi rs + u, a 2 dim rs
+#     (3D FP32 D3Q19: 152 + 4 + 24 = 180 B)
+#   whole step: + the phi pass (g QG rs + phi rs; or phi rs for the flags alone)
+#     + the finite-difference update (phi, u, a read, phi written: (2 + 2 dim) rs)
+def model_bytes(p):
+    rs = 8 if p.precision == "fp64" else 4
+    fs = {"fp64": 8, "fp32": 4, "fp16": 2, "bf16": 2}[p.precision]
+    q = 9 if p.dim == 2 else p.hydro_q
+    qg = 9 if p.dim == 2 else 7
+    if p.cac_solver:
+        collide = 2 * q * fs + rs + 2 * p.dim * rs
+        return collide, collide + rs + (2 + 2 * p.dim) * rs
+    collide = 2 * q * fs + 2 * qg * rs + rs
+    return collide, collide + qg * rs + rs
 
 
 def kernel_hash() -> str:
@@ -56,7 +59,7 @@ def kernel_hash() -> str:
 def workload_key(args) -> str:
     key = (f"{args.workload} n={args.n} bubbles={args.bubbles} r={args.rmin:g}-{args.rmax:g} "
            f"gap={args.gap:g} {args.precision}")
-    return key + (" muscl" if args.phase_field == "muscl" else "")
+    return key + (" muscl" if args.phase_field == "muscl" else "") + (" d3q27" if args.hydro_q == 27 else "")
 
 
 def traffic_from_profile(args):
@@ -87,9 +90,12 @@ def make_workload(args):
     else:
         st = W.config_collision_3d(precision=args.precision)
         desc = f"droplet collision 256x128x128, D3Q19+D3Q7, {args.precision}"
-    st.params = st.params.replace(diag_interval=args.diag, cac_solver=1 if args.phase_field == "muscl" else 0)
+    st.params = st.params.replace(diag_interval=args.diag, cac_solver=1 if args.phase_field == "muscl" else 0,
+                                  hydro_q=args.hydro_q)
     if args.phase_field == "muscl":
         desc += ", finite-difference MUSCL-TVD phase field"
+    if args.hydro_q == 27:
+        desc = desc.replace("D3Q19", "D3Q27")
     return st, desc
 
 
@@ -102,7 +108,7 @@ def cpu_baseline(args):
     bubbles = max(1, int(round(args.bubbles * (n / args.n) ** 3)))
     st = W.config_swarm(n=n, bubbles=bubbles, rmin=args.rmin, rmax=args.rmax, gap=args.gap, precision="fp64")
     fd = args.phase_field == "muscl"
-    o = Oracle(st.params.replace(cac_solver=1 if fd else 0))
+    o = Oracle(st.params.replace(cac_solver=1 if fd else 0, hydro_q=args.hydro_q))
     o.init_fields(st.phi, st.u)
     o.step(1)
     t0 = time.perf_counter()
@@ -112,7 +118,8 @@ def cpu_baseline(args):
     return {"value": round(mlups, 3), "unit": "MLUPS", "cores": o.lib.oracle_threads(),
             "kind": "oracle",
             "sample": f"swarm recipe on {n}^3 ({bubbles} bubbles), FP64 oracle"
-                      f"{' (MUSCL phase field)' if fd else ''}, {args.cpu_steps} steps, {dt:.1f} s"}
+                      f"{' (MUSCL phase field)' if fd else ''}{' (D3Q27)' if args.hydro_q == 27 else ''}, "
+                      f"{args.cpu_steps} steps, {dt:.1f} s"}
 
 
 def serving_report(args):
@@ -148,6 +155,8 @@ def main():
     ap.add_argument("--gap", type=float, default=3.0)
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp16", "bf16", "fp64"])
     ap.add_argument("--diag", type=int, default=100)
+    ap.add_argument("--hydro-q", type=int, default=19, choices=[19, 27],
+                    help="3D hydrodynamic lattice: D3Q19 or the paper's D3Q27")
     ap.add_argument("--phase-field", default="lbm", choices=["lbm", "muscl"],
                     help="phase-field solver: lattice Boltzmann (Sec. 2.1.2) or finite-difference MUSCL-TVD "
                          "(Sec. 2.1.1)")
@@ -236,9 +245,8 @@ def main():
     tiles = gated.reshape(p.nz // t, t, p.ny // 8, 8, p.nx // 8, 8).any(axis=(1, 3, 5)).sum()
     tile_cells = int(tiles) * 8 * 8 * t
     real = 8 if p.precision == "fp64" else 4
-    fd = p.cac_solver != 0
-    step_bytes = (STEP_BYTES_FD if fd else STEP_BYTES).get((p.precision, p.dim))
-    bytes_launch = (COLLIDE_BYTES_FD if fd else COLLIDE_BYTES)[(p.precision, p.dim)] * N + p.dim * real * tile_cells
+    collide_bytes, step_bytes = model_bytes(p)
+    bytes_launch = collide_bytes * N + p.dim * real * tile_cells
     coll_ms, coll_n = kt["collide"]
     avg_s = coll_ms / coll_n / 1e3
     achieved = bytes_launch / avg_s / 1e9
@@ -264,7 +272,7 @@ def main():
                      "bytes_per_launch": bytes_launch,
                      "avg_launch_ms": round(avg_s * 1e3, 4),
                      "step_model_bytes_per_cell": step_bytes,
-                     "step_frac": round((step_bytes or 0) * N / (ms_step / 1e3) / 1e9 / PEAK_HBM_GBS, 4)},
+                     "step_frac": round(step_bytes * N / (ms_step / 1e3) / 1e9 / PEAK_HBM_GBS, 4)},
         "kernel_ms_per_launch": {k: round(v[0] / max(v[1], 1), 4) for k, v in kt.items()},
         "copy_gbs": round(copy_gbs, 1),
         "state": {"step": diag["step"], "n_bubbles": diag["n_droplets"], "nci_active": diag["nci_active"],

@@ -89,6 +89,10 @@ typedef struct {
                                 limiter, upwind face fluxes, isotropic Laplacian and
                                 sharpening divergence), phi stored and double-buffered.
                                 Not supported by lbm_batch_step.                        */
+  int hydro_q;               /* 3D hydrodynamic lattice: 0 or 19 D3Q19, 27 D3Q27 (the
+                                paper's lattice, Sec. 2.1; also the weights of the
+                                isotropic gradient, Laplacian and divergence stencils).
+                                2D: 0 or 9 (D2Q9).                                      */
 } lbm_params;
 
 typedef struct {
@@ -175,9 +179,10 @@ int lbm_diag_history(lbm_ctx* ctx, lbm_diag* out, int max);
 int lbm_timing(lbm_ctx* ctx, int enable);
 int lbm_kernel_times(lbm_ctx* ctx, double* ms, long* counts);
 
-/* Lattice velocity order used by the population calls: which 0 = hydrodynamic
- * lattice, 1 = phase-field lattice of a dim-dimensional context; c receives
- * 3*q ints (cx, cy, cz per velocity).  Returns q. */
+/* Lattice velocity order used by the population calls: which 0 = default
+ * hydrodynamic lattice (D2Q9 / D3Q19), 1 = phase-field lattice (D2Q9 / D3Q7),
+ * 2 = D3Q27 (dim 3 only); c (may be null) receives 3*q ints (cx, cy, cz per
+ * velocity).  Returns q, or LBM_E_INVALID. */
 int lbm_lattice(int dim, int which, int* c);
 /* Incoming populations of the current state on the periodic box
  * [x0, x0+bx) x [y0, y0+by) x [z0, z0+bz) (wrapped), SoA [q][bz][by][bx]. */
@@ -203,7 +208,7 @@ int lbm_load_state(lbm_ctx* ctx, const void* host_buf, size_t bytes);
  * graph captured on the first call for this ordered set of contexts (cached,
  * at most 8 sets; lbm_destroy drops the sets that hold a context); the
  * remaining n % 8 steps are launched directly.  All contexts must live on the
- * same device, share dimension and precision, be initialised and appear once.
+ * same device, share lattice and precision, be initialised and appear once.
  * Their populations after the call equal bit for bit those of lbm_step on each
  * alone; periodic diagnostics (diag_interval) are not taken inside a batch.
  * Enqueued on the first context's stream after the others' streams have been

@@ -246,11 +246,13 @@ __device__ __forceinline__ T ccdot(int cx, int cy, int cz, const T A[6]) {
   return d + (T)2 * sdot(cx * cy, cx * cz, cy * cz, A[3], A[4], A[5]);
 }
 
-// Isotropic gradient and Laplacian with the hydrodynamic lattice weights
-// (Eqs. grad_iso, lap_iso; 1/cs^2 = 3).  get(i) returns psi(x + c_i).
-template <int DIM, typename T, typename G>
+// Isotropic gradient and Laplacian with the weights of the hydrodynamic lattice
+// of QH velocities (Eqs. grad_iso, lap_iso; 1/cs^2 = 3).  get(i) returns
+// psi(x + c_i).
+template <int QH, typename T, typename G>
 __device__ __forceinline__ void grad_lap(const G& get, T gr[3], T& lap) {
-  using L = Hydro<DIM>;
+  using L = HydroQ<QH>;
+  constexpr int DIM = L::D;
   T g0 = 0, g1 = 0, g2 = 0, sn = 0;
 #pragma unroll
   for (int i = 1; i < L::Q; i += 2) {
@@ -446,13 +448,13 @@ __device__ __forceinline__ void nci_clear_other(unsigned* __restrict__ flags_oth
 // within tie_eps of that dot; the planes are combined with wave shuffles;
 // (5) the group leader builds J (Sec. 2.3.3) and the tile's J is written from
 // LDS, zero for cells without a partner.
-template <int DIM, typename T, bool DEBUG, int WR>
+template <int DIM, int QH, typename T, bool DEBUG, int WR>
 __device__ __forceinline__ void nci_tile(NciShared<DIM, T>& sm, unsigned t, const T* __restrict__ phi,
                                          T* __restrict__ J, int* __restrict__ chi_out,
                                          int* __restrict__ part_out, const Geo& geo, const NciP& np,
                                          unsigned& my_active) {
   using TL = NciTile<DIM, T>;
-  using L = Hydro<DIM>;
+  using L = HydroQ<QH>;
   constexpr int TX = TL::TX, TY = TL::TY, TZ = TL::TZ;
   constexpr int TC = TX * TY * TZ;
   constexpr int PX = NciShared<DIM, T>::PX, PY = NciShared<DIM, T>::PY;
@@ -497,7 +499,7 @@ __device__ __forceinline__ void nci_tile(NciShared<DIM, T>& sm, unsigned t, cons
         NQ<T> v{(T)0, (T)0, (T)0, pc * ((T)1 - pc)};
         if (v.q >= q_th) {
           T gr[3], lap;
-          grad_lap<DIM, T>([&](int i) { return sm.phs[c + L::cx[i] + PX * (L::cy[i] + PY * L::cz[i])]; },
+          grad_lap<QH, T>([&](int i) { return sm.phs[c + L::cx[i] + PX * (L::cy[i] + PY * L::cz[i])]; },
                            gr, lap);
           T mag = gr[0] * gr[0] + gr[1] * gr[1];
           if (DIM == 3) mag += gr[2] * gr[2];
@@ -740,17 +742,17 @@ __device__ __forceinline__ void nci_tile(NciShared<DIM, T>& sm, unsigned t, cons
 }
 
 // The tile routine with the window radius as a compile-time constant.
-template <int DIM, typename T, bool DEBUG>
+template <int DIM, int QH, typename T, bool DEBUG>
 __device__ __forceinline__ void nci_tile_w(NciShared<DIM, T>& sm, unsigned t, const T* __restrict__ phi,
                                            T* __restrict__ J, int* __restrict__ chi_out,
                                            int* __restrict__ part_out, const Geo& geo, const NciP& np,
                                            unsigned& my_active) {
-  if (np.w == 3) nci_tile<DIM, T, DEBUG, 3>(sm, t, phi, J, chi_out, part_out, geo, np, my_active);
-  else if (np.w == 2) nci_tile<DIM, T, DEBUG, 2>(sm, t, phi, J, chi_out, part_out, geo, np, my_active);
-  else nci_tile<DIM, T, DEBUG, 1>(sm, t, phi, J, chi_out, part_out, geo, np, my_active);
+  if (np.w == 3) nci_tile<DIM, QH, T, DEBUG, 3>(sm, t, phi, J, chi_out, part_out, geo, np, my_active);
+  else if (np.w == 2) nci_tile<DIM, QH, T, DEBUG, 2>(sm, t, phi, J, chi_out, part_out, geo, np, my_active);
+  else nci_tile<DIM, QH, T, DEBUG, 1>(sm, t, phi, J, chi_out, part_out, geo, np, my_active);
 }
 
-template <int DIM, typename T, bool DEBUG>
+template <int DIM, int QH, typename T, bool DEBUG>
 __global__ __launch_bounds__(NT_NCI) void k_nci(const T* __restrict__ phi, T* __restrict__ J,
                                                 int* __restrict__ chi_out, int* __restrict__ part_out,
                                                 const unsigned* __restrict__ list,
@@ -764,7 +766,7 @@ __global__ __launch_bounds__(NT_NCI) void k_nci(const T* __restrict__ phi, T* __
   const unsigned ntiles = *cnt;
   unsigned my_active = 0;
   for (unsigned k = blockIdx.x; k < ntiles; k += gridDim.x)
-    nci_tile_w<DIM, T, DEBUG>(sm, list[k], phi, J, chi_out, part_out, geo, np, my_active);
+    nci_tile_w<DIM, QH, T, DEBUG>(sm, list[k], phi, J, chi_out, part_out, geo, np, my_active);
   my_active = wave_sum(my_active);
   if ((threadIdx.x & 63) == 0 && my_active) atomicAdd(nci_count, my_active);
 }
@@ -805,7 +807,7 @@ struct Planes {
 template <typename T>
 struct PhysT {
   T rho_g, drho, mu_a, mu_b, beta4, kappa, rho_mean, g[3], kc, inv_tau_phi, eps_n;
-  T fref[19];   // w_i pstar_ref: offset of the 16-bit population encoding
+  T fref[27];   // w_i pstar_ref: offset of the 16-bit population encoding
 };
 
 __device__ __forceinline__ float m_rcp(float a) { return __builtin_amdgcn_rcpf(a); }
@@ -824,14 +826,14 @@ __device__ __forceinline__ double m_rcp(double a) { return 1.0 / a; }
 // the populations in place; MODE_STEP_DIAG also fills acc with the cell's
 // contributions to the FP64 diagnostics; MODE_DRY leaves the populations and
 // writes p*, rho, u, F to macro (when given).
-template <int DIM, int PAR, int MODE, typename T, typename FS, typename GS, bool OFF32>
+template <int DIM, int QH, int PAR, int MODE, typename T, typename FS, typename GS, bool OFF32>
 __device__ __forceinline__ void collide_cell(const Planes<FS, GS>& pl, const T* __restrict__ phi,
                                              const T* __restrict__ J,
                                              const unsigned* __restrict__ flags, const Geo& geo,
                                              const PhysT<T>& pp, int nci_on, T* __restrict__ macro,
                                              T* __restrict__ uout, int x, int y, int z,
                                              double acc[NPART]) {
-  using H = Hydro<DIM>;
+  using H = HydroQ<QH>;
   using P = Phase<DIM>;
   using TL = NciTile<DIM, T>;
   constexpr int Q = H::Q, QG = P::Q;
@@ -840,7 +842,7 @@ __device__ __forceinline__ void collide_cell(const Planes<FS, GS>& pl, const T* 
   const long long S = geo.S;
   // ---- phase field around the cell: grad, lap, mu_phi
   T gr[3], lap;
-  grad_lap<DIM, T>([&](int i) { return *plane_at<OFF32>(phi, (unsigned)nb(H::cx[i], H::cy[i], H::cz[i])); },
+  grad_lap<QH, T>([&](int i) { return *plane_at<OFF32>(phi, (unsigned)nb(H::cx[i], H::cy[i], H::cz[i])); },
                    gr, lap);
   const T ph = *plane_at<OFF32>(phi, idx);
   T gmag = gr[0] * gr[0] + gr[1] * gr[1];
@@ -1052,7 +1054,7 @@ __device__ __forceinline__ void collide_cell(const Planes<FS, GS>& pl, const T* 
   }
 }
 
-template <int DIM, int PAR, int MODE, typename T, typename FS, typename GS, bool OFF32>
+template <int DIM, int QH, int PAR, int MODE, typename T, typename FS, typename GS, bool OFF32>
 __global__ __launch_bounds__(NT) void k_collide(Planes<FS, GS> pl, const T* __restrict__ phi,
                                                 const T* __restrict__ J,
                                                 const unsigned* __restrict__ flags,
@@ -1065,7 +1067,9 @@ __global__ __launch_bounds__(NT) void k_collide(Planes<FS, GS> pl, const T* __re
   const bool valid = x < geo.nx && y < geo.ny;
   double acc[NPART] = {};
   if (MODE == MODE_STEP && !valid) return;
-  if (valid) collide_cell<DIM, PAR, MODE, T, FS, GS, OFF32>(pl, phi, J, flags, geo, pp, nci_on, macro, uout, x, y, z, acc);
+  if (valid)
+    collide_cell<DIM, QH, PAR, MODE, T, FS, GS, OFF32>(pl, phi, J, flags, geo, pp, nci_on, macro, uout, x, y, z,
+                                                       acc);
   if constexpr (MODE != MODE_STEP) block_partials(acc, partials);
 }
 
@@ -1128,11 +1132,11 @@ __device__ __forceinline__ T flux_difference(const PH& ph, const UV& uv, int ax)
 // approximately, and that residue would add mass every step), and the
 // increment is formed before it is added to phi (added term by term, parts
 // smaller than half an ulp of phi would each be rounded away).
-template <int DIM, typename T, typename PH, typename AV>
+template <int DIM, int QH, typename T, typename PH, typename AV>
 __device__ __forceinline__ T muscl_increment(const PH& ph, const AV& av, T div, T mob, T kap) {
-  using H = Hydro<DIM>;
+  using H = HydroQ<QH>;
   const T pc = ph(0, 0, 0);
-  T sl[2] = {0, 0}, dc[2] = {0, 0};
+  T sl[3] = {0, 0, 0}, dc[3] = {0, 0, 0};
 #pragma unroll
   for (int i = 1; i < H::Q; i += 2) {
     const int c[3] = {H::cx[i], H::cy[i], H::cz[i]};
@@ -1145,15 +1149,21 @@ __device__ __forceinline__ T muscl_increment(const PH& ph, const AV& av, T div, 
       dc[cl] += c[a] > 0 ? d : -d;
     }
   }
-  const T w1 = wt<H, T>(1), w2 = wt<H, T>(H::Q - 1);
-  const T lap = (T)6 * (w1 * sl[0] + w2 * sl[1]);
-  const T dvi = (T)3 * (w1 * dc[0] + w2 * dc[1]);
+  // one weight per speed class |c|^2 = 1, 2 (and 3 on D3Q27): directions 1, 7, 19
+  const T w1 = wt<H, T>(1), w2 = wt<H, T>(DIM == 2 ? 5 : 7);
+  T lap = w1 * sl[0] + w2 * sl[1], dvi = w1 * dc[0] + w2 * dc[1];
+  if constexpr (QH == 27) {
+    lap += wt<H, T>(19) * sl[2];
+    dvi += wt<H, T>(19) * dc[2];
+  }
+  lap = (T)6 * lap;
+  dvi = (T)3 * dvi;
   return (mob * lap - div) - kap * dvi;
 }
 
 // One cell per thread, neighbours read from global memory (2D boxes).  ua holds
 // u (DIM planes) then a (DIM planes), plane stride S; out must not alias phi.
-template <int DIM, typename T>
+template <int DIM, int QH, typename T>
 __global__ __launch_bounds__(NT) void k_muscl(const T* __restrict__ phi, T* __restrict__ out,
                                               const T* __restrict__ ua, Geo geo, T mob, T kap) {
   int x, y, z;
@@ -1179,7 +1189,7 @@ __global__ __launch_bounds__(NT) void k_muscl(const T* __restrict__ phi, T* __re
   T div = 0;
 #pragma unroll
   for (int ax = 0; ax < DIM; ++ax) div += flux_difference<T>(ph, uv, ax);
-  const T inc = muscl_increment<DIM, T>(
+  const T inc = muscl_increment<DIM, QH, T>(
       ph, [&](int a, int dx, int dy, int dz) { return A[a * S + off(dx, dy, dz)]; }, div, mob, kap);
   out[idx] = phi[idx] + inc;
 }
@@ -1208,7 +1218,7 @@ struct MuslTile {
   static constexpr int KP = (PN + NT - 1) / NT, KA = (AN + NT - 1) / NT;   // staged cells per thread
 };
 
-template <typename T>
+template <int QH, typename T>
 __global__ __launch_bounds__(MuslTile<T>::NT) void k_muscl3(const T* __restrict__ phi, T* __restrict__ out,
                                                             const T* __restrict__ ua, Geo geo, T mob, T kap,
                                                             int ntx, int nty) {
@@ -1335,7 +1345,7 @@ __global__ __launch_bounds__(MuslTile<T>::NT) void k_muscl3(const T* __restrict_
       const T fzp = face_flux(q1, q2, q3, q4, (T)0.5 * (v1 + v2));
       const T div = (flux_difference<T>(ph, uv, 0) + flux_difference<T>(ph, uv, 1)) + (fzp - fzm);
       fzm = fzp;
-      const T inc = muscl_increment<3, T>(ph, av, div, mob, kap);
+      const T inc = muscl_increment<3, QH, T>(ph, av, div, mob, kap);
       *(T*)((char*)(out + (long long)z * plane) + owno) = q2 + inc;
     }
     __syncthreads();
@@ -1501,11 +1511,11 @@ __global__ __launch_bounds__(NT) void k_reduce(const double* __restrict__ pa, in
 // ---------------------------------------------------------------------------
 
 // f = feq(p*, u) (Eq. feq3), g = geq(phi, u, n) in natural layout (parity 0).
-template <int DIM, typename T, typename FS, typename GS>
+template <int DIM, int QH, typename T, typename FS, typename GS>
 __global__ __launch_bounds__(NT) void k_init(FS* __restrict__ f, GS* __restrict__ g,
                                              const T* __restrict__ phi, const T* __restrict__ uin,
                                              const T* __restrict__ psin, Geo geo, PhysT<T> pp) {
-  using H = Hydro<DIM>;
+  using H = HydroQ<QH>;
   using P = Phase<DIM>;
   const int t = swizzled_block();
   const int bx = t % geo.nbx, r = t / geo.nbx, by = r % geo.nby, z = r / geo.nby;
@@ -1527,7 +1537,7 @@ __global__ __launch_bounds__(NT) void k_init(FS* __restrict__ f, GS* __restrict_
     Store<FS>::st(f + pop_elem(i, x, y, z, geo, H::Q), fe, pp.fref[i]);
   }
   T gr[3], lap;
-  grad_lap<DIM, T>([&](int i) { return phi[nb(H::cx[i], H::cy[i], H::cz[i])]; }, gr, lap);
+  grad_lap<QH, T>([&](int i) { return phi[nb(H::cx[i], H::cy[i], H::cz[i])]; }, gr, lap);
   const T ph = phi[idx];
   T gmag = m_sqrt(gr[0] * gr[0] + gr[1] * gr[1] + gr[2] * gr[2]);
   const T kc = pp.kc * ph * ((T)1 - ph) / (gmag + pp.eps_n);
@@ -1540,12 +1550,12 @@ __global__ __launch_bounds__(NT) void k_init(FS* __restrict__ f, GS* __restrict_
 }
 
 // Incoming populations on a wrapped box, as doubles, SoA [q][box].
-template <int DIM, int PAR, typename T, typename FS, typename GS>
+template <int DIM, int QH, int PAR, typename T, typename FS, typename GS>
 __global__ __launch_bounds__(NT) void k_getpop(const FS* __restrict__ f, const GS* __restrict__ g,
                                                Geo geo, PhysT<T> pp, int x0, int y0, int z0, int bxn,
                                                int byn, int bzn, double* __restrict__ fo,
                                                double* __restrict__ go) {
-  using H = Hydro<DIM>;
+  using H = HydroQ<QH>;
   using P = Phase<DIM>;
   const long long B = (long long)bxn * byn * bzn;
   const long long e = (long long)blockIdx.x * NT + threadIdx.x;
@@ -1567,11 +1577,11 @@ __global__ __launch_bounds__(NT) void k_getpop(const FS* __restrict__ f, const G
 }
 
 // Whole-field populations (doubles, SoA [q][N]) into natural layout.
-template <int DIM, typename T, typename FS, typename GS>
+template <int DIM, int QH, typename T, typename FS, typename GS>
 __global__ __launch_bounds__(NT) void k_setpop(FS* __restrict__ f, GS* __restrict__ g, Geo geo,
                                                PhysT<T> pp, const double* __restrict__ fi,
                                                const double* __restrict__ gi) {
-  using H = Hydro<DIM>;
+  using H = HydroQ<QH>;
   using P = Phase<DIM>;
   const long long N = (long long)geo.nx * geo.ny * geo.nz;
   const long long e = (long long)blockIdx.x * NT + threadIdx.x;
@@ -1638,7 +1648,7 @@ __global__ __launch_bounds__(NT) void k_phi_multi(const Job<T, FS, GS>* __restri
                             jb.nci_on, jb.q_th, x, y, z);
 }
 
-template <int DIM, typename T, typename FS, typename GS>
+template <int DIM, int QH, typename T, typename FS, typename GS>
 __global__ __launch_bounds__(NT_NCI) void k_nci_multi(const Job<T, FS, GS>* __restrict__ jobs,
                                                       int njobs, int s) {
   __shared__ NciShared<DIM, T> sm;
@@ -1650,13 +1660,13 @@ __global__ __launch_bounds__(NT_NCI) void k_nci_multi(const Job<T, FS, GS>* __re
     const unsigned ntiles = jb.cnt[par];
     unsigned act = 0;
     for (unsigned k = blockIdx.x; k < ntiles; k += gridDim.x)
-      nci_tile_w<DIM, T, false>(sm, jb.list[par][k], jb.phi, jb.J, nullptr, nullptr, jb.geo, jb.np, act);
+      nci_tile_w<DIM, QH, T, false>(sm, jb.list[par][k], jb.phi, jb.J, nullptr, nullptr, jb.geo, jb.np, act);
     act = wave_sum(act);
     if ((threadIdx.x & 63) == 0 && act) atomicAdd(jb.cnt + 2, act);
   }
 }
 
-template <int DIM, typename T, typename FS, typename GS, bool OFF32>
+template <int DIM, int QH, typename T, typename FS, typename GS, bool OFF32>
 __global__ __launch_bounds__(NT) void k_collide_multi(const Job<T, FS, GS>* __restrict__ jobs,
                                                       int njobs, int s) {
   const int t = swizzled_block();
@@ -1669,10 +1679,10 @@ __global__ __launch_bounds__(NT) void k_collide_multi(const Job<T, FS, GS>* __re
   if (x >= jb.geo.nx || y >= jb.geo.ny) return;
   double acc[NPART];
   if (par == 0)
-    collide_cell<DIM, 0, MODE_STEP, T, FS, GS, OFF32>(jb.pl, jb.phi, jb.J, jb.flags[0], jb.geo, jb.pp,
+    collide_cell<DIM, QH, 0, MODE_STEP, T, FS, GS, OFF32>(jb.pl, jb.phi, jb.J, jb.flags[0], jb.geo, jb.pp,
                                                       jb.nci_on, nullptr, nullptr, x, y, z, acc);
   else
-    collide_cell<DIM, 1, MODE_STEP, T, FS, GS, OFF32>(jb.pl, jb.phi, jb.J, jb.flags[1], jb.geo, jb.pp,
+    collide_cell<DIM, QH, 1, MODE_STEP, T, FS, GS, OFF32>(jb.pl, jb.phi, jb.J, jb.flags[1], jb.geo, jb.pp,
                                                       jb.nci_on, nullptr, nullptr, x, y, z, acc);
 }
 

@@ -1,6 +1,6 @@
 // lattice.hpp -- velocity sets of the coupled step (device side).
 //
-// Hydrodynamics: D2Q9 / D3Q19 with cs^2 = 1/3.  Phase field: D2Q9 (cs^2 = 1/3)
+// Hydrodynamics: D2Q9 / D3Q19 / D3Q27 with cs^2 = 1/3.  Phase field: D2Q9 (cs^2 = 1/3)
 // in 2D and D3Q7 (w0 = 1/4, axis 1/8, cs^2 = 1/4) in 3D.  Velocities are ordered
 // rest first, then opposite pairs (2k-1, 2k), so that the collision can evaluate
 // the even and odd parts of each pair once (c_{2k} = -c_{2k-1}).
@@ -15,11 +15,13 @@ namespace lbm {
 // plain rounded weights the D2Q9 sum is 1 + 7.45e-9, which makes every FP32
 // step scale the phase-field mass by (1 + 7.45e-9 / tau_phi).
 
-template <int DIM>
-struct Hydro;
+// Hydrodynamic lattices by velocity count: 9 (D2Q9), 19 (D3Q19), 27 (D3Q27).
+template <int QH>
+struct HydroQ;
 
 template <>
-struct Hydro<2> {
+struct HydroQ<9> {
+  static constexpr int D = 2;
   static constexpr int Q = 9;
   static constexpr int cx[9] = {0, 1, -1, 0, 0, 1, -1, 1, -1};
   static constexpr int cy[9] = {0, 0, 0, 1, -1, 1, -1, -1, 1};
@@ -32,7 +34,8 @@ struct Hydro<2> {
 };
 
 template <>
-struct Hydro<3> {
+struct HydroQ<19> {
+  static constexpr int D = 3;
   static constexpr int Q = 19;
   static constexpr int cx[19] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
   static constexpr int cy[19] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
@@ -47,6 +50,36 @@ struct Hydro<3> {
                                    0x1.c71c70p-6f, 0x1.c71c70p-6f, 0x1.c71c70p-6f, 0x1.c71c70p-6f,
                                    0x1.c71c70p-6f, 0x1.c71c70p-6f, 0x1.c71c70p-6f};
 };
+
+// D3Q27, the tensor product of the D1Q3 weights (2/3, 1/6, 1/6): rest 8/27,
+// axis 2/27, face diagonal 1/54, body diagonal 1/216.  FP32: the rest weight is
+// one ulp below its nearest float and the face-diagonal ones one ulp above.
+template <>
+struct HydroQ<27> {
+  static constexpr int D = 3;
+  static constexpr int Q = 27;
+  static constexpr int cx[27] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0,
+                                 1, -1, 1, -1, 1, -1, -1, 1};
+  static constexpr int cy[27] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1,
+                                 1, -1, 1, -1, -1, 1, 1, -1};
+  static constexpr int cz[27] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1,
+                                 1, -1, -1, 1, 1, -1, 1, -1};
+  static constexpr double w[27] = {8.0 / 27,  2.0 / 27,  2.0 / 27,  2.0 / 27,  2.0 / 27,  2.0 / 27,
+                                   2.0 / 27,  1.0 / 54,  1.0 / 54,  1.0 / 54,  1.0 / 54,  1.0 / 54,
+                                   1.0 / 54,  1.0 / 54,  1.0 / 54,  1.0 / 54,  1.0 / 54,  1.0 / 54,
+                                   1.0 / 54,  1.0 / 216, 1.0 / 216, 1.0 / 216, 1.0 / 216, 1.0 / 216,
+                                   1.0 / 216, 1.0 / 216, 1.0 / 216};
+  static constexpr float wf[27] = {
+      0x1.2f684ap-2f, 0x1.2f684cp-4f, 0x1.2f684cp-4f, 0x1.2f684cp-4f, 0x1.2f684cp-4f, 0x1.2f684cp-4f,
+      0x1.2f684cp-4f, 0x1.2f684ep-6f, 0x1.2f684ep-6f, 0x1.2f684ep-6f, 0x1.2f684ep-6f, 0x1.2f684ep-6f,
+      0x1.2f684ep-6f, 0x1.2f684ep-6f, 0x1.2f684ep-6f, 0x1.2f684ep-6f, 0x1.2f684ep-6f, 0x1.2f684ep-6f,
+      0x1.2f684ep-6f, 0x1.2f684cp-8f, 0x1.2f684cp-8f, 0x1.2f684cp-8f, 0x1.2f684cp-8f, 0x1.2f684cp-8f,
+      0x1.2f684cp-8f, 0x1.2f684cp-8f, 0x1.2f684cp-8f};
+};
+
+// The default hydrodynamic lattice of each dimension.
+template <int DIM>
+using Hydro = HydroQ<DIM == 2 ? 9 : 19>;
 
 template <int DIM>
 struct Phase;

@@ -31,6 +31,7 @@ thread_local std::string g_create_error;
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
 int q_hydro(int dim) { return dim == 2 ? 9 : 19; }
+int q_hydro(const lbm_params* p) { return p->dim == 2 ? 9 : (p->hydro_q == 27 ? 27 : 19); }
 int q_phase(int dim) { return dim == 2 ? 9 : 7; }
 
 size_t real_size(int prec) { return prec == LBM_FP64 ? 8 : 4; }
@@ -65,7 +66,11 @@ bool valid_params(const lbm_params* p, std::string* why) {
   if (p->dim == 2 && p->nz != 1) return bad("2D boxes need nz = 1");
   const long long N = (long long)p->nx * p->ny * p->nz;
   if (N >= (1LL << 31) - 4096) return bad("box too large (more than 2^31 cells)");
-  if ((long long)p->nx * p->ny * 19 >= (1LL << 32)) return bad("z plane too large (nx ny 19 must be below 2^32)");
+  if (p->dim == 3 ? (p->hydro_q != 0 && p->hydro_q != 19 && p->hydro_q != 27)
+                  : (p->hydro_q != 0 && p->hydro_q != 9))
+    return bad("hydro_q must be 0, 19 or 27 in 3D (0 or 9 in 2D)");
+  if ((long long)p->nx * p->ny * q_hydro(p) >= (1LL << 32))
+    return bad("z plane too large (nx ny q must be below 2^32)");
   if (p->precision < LBM_FP64 || p->precision > LBM_FP32_BF16STORE) return bad("unknown precision");
   if (!(p->tau > 0.5)) return bad("tau must exceed 1/2");
   if (!(p->visc_ratio > 0)) return bad("visc_ratio must be positive");
@@ -113,7 +118,7 @@ Layout make_layout(const lbm_params* p) {
   L.ntiles = L.ntx * L.nty * L.ntz;
   const size_t rs = real_size(p->precision), fs = fstore_size(p->precision);
   size_t o = 0;
-  L.off_f = o;   o = align256(o + (size_t)q_hydro(p->dim) * L.N * fs);
+  L.off_f = o;   o = align256(o + (size_t)q_hydro(p) * L.N * fs);
   L.off_g = o;   o = align256(o + (size_t)q_phase(p->dim) * L.N * rs);
   L.off_phi = o; o = align256(o + (size_t)L.S * rs);
   L.off_J = o;   o = align256(o + (size_t)p->dim * L.S * rs);
@@ -309,7 +314,7 @@ void fill_diag(const double* r, long step, lbm_diag* d) {
   d->max_frep = r[12];
 }
 
-template <int DIM, typename T, typename FS, typename GS>
+template <int DIM, int QH, typename T, typename FS, typename GS>
 struct Engine {
   static dim3 rows(const lbm_ctx* c) { return dim3((unsigned)c->L.nblk); }
 
@@ -328,7 +333,7 @@ struct Engine {
     q.kc = (T)P.kc;
     q.inv_tau_phi = (T)P.inv_tau_phi;
     q.eps_n = (T)P.eps_n;
-    for (int i = 0; i < Hydro<DIM>::Q; ++i) q.fref[i] = (T)(Hydro<DIM>::w[i] * P.pstar_ref);
+    for (int i = 0; i < HydroQ<QH>::Q; ++i) q.fref[i] = (T)(HydroQ<QH>::w[i] * P.pstar_ref);
     return q;
   }
 
@@ -350,12 +355,12 @@ struct Engine {
     const int grid = std::min(NCI_GRID, std::max(1, c->L.ntiles));
     Timed tm(c, 1);
     if (chi) {
-      hipLaunchKernelGGL((k_nci<DIM, T, true>), dim3(grid), dim3(NT_NCI), 0, c->stream,
+      hipLaunchKernelGGL((k_nci<DIM, QH, T, true>), dim3(grid), dim3(NT_NCI), 0, c->stream,
                          (const T*)c->phi(), (T*)c->J(), chi, part, c->list(par), c->cnt() + par,
                          c->flags(1 - par), c->list(1 - par), c->cnt() + (1 - par), c->cnt() + 2,
                          c->geo, c->nci);
     } else {
-      hipLaunchKernelGGL((k_nci<DIM, T, false>), dim3(grid), dim3(NT_NCI), 0, c->stream,
+      hipLaunchKernelGGL((k_nci<DIM, QH, T, false>), dim3(grid), dim3(NT_NCI), 0, c->stream,
                          (const T*)c->phi(), (T*)c->J(), (int*)nullptr, (int*)nullptr, c->list(par),
                          c->cnt() + par, c->flags(1 - par), c->list(1 - par), c->cnt() + (1 - par),
                          c->cnt() + 2, c->geo, c->nci);
@@ -373,7 +378,7 @@ struct Engine {
   // phi / J plane stay below 4 GiB.
   static bool off32(const lbm_ctx* c) {
     const size_t plane = (size_t)c->p.nx * c->p.ny;
-    const size_t widest = std::max(plane * Hydro<DIM>::Q * sizeof(FS),
+    const size_t widest = std::max(plane * HydroQ<QH>::Q * sizeof(FS),
                                    std::max(plane * Phase<DIM>::Q * sizeof(GS), (size_t)c->L.S * sizeof(T)));
     return widest < (size_t(1) << 32);
   }
@@ -381,8 +386,9 @@ struct Engine {
   template <int MODE>
   static void collide_pass(lbm_ctx* c, int par, T* macro) {
     const bool o32 = off32(c);
-    auto k = par == 0 ? (o32 ? k_collide<DIM, 0, MODE, T, FS, GS, true> : k_collide<DIM, 0, MODE, T, FS, GS, false>)
-                      : (o32 ? k_collide<DIM, 1, MODE, T, FS, GS, true> : k_collide<DIM, 1, MODE, T, FS, GS, false>);
+    auto k = par == 0
+                 ? (o32 ? k_collide<DIM, QH, 0, MODE, T, FS, GS, true> : k_collide<DIM, QH, 0, MODE, T, FS, GS, false>)
+                 : (o32 ? k_collide<DIM, QH, 1, MODE, T, FS, GS, true> : k_collide<DIM, QH, 1, MODE, T, FS, GS, false>);
     Timed tm(c, 2);
     hipLaunchKernelGGL(k, rows(c), dim3(NT), 0, c->stream, planes(c),
                        (const T*)c->phi(), (const T*)c->J(), (const unsigned*)c->flags(par),
@@ -400,11 +406,11 @@ struct Engine {
         using M = MuslTile<T>;
         const int ntx = (c->p.nx + MZ_TX - 1) / MZ_TX, nty = (c->p.ny + M::TY - 1) / M::TY;
         const int nzc = (c->p.nz + MUSCL_ZRUN - 1) / MUSCL_ZRUN;
-        hipLaunchKernelGGL((k_muscl3<T>), dim3((unsigned)(ntx * nty * nzc)), dim3(M::NT), 0, c->stream,
+        hipLaunchKernelGGL((k_muscl3<QH, T>), dim3((unsigned)(ntx * nty * nzc)), dim3(M::NT), 0, c->stream,
                            (const T*)c->phi(), (T*)c->phi_next(), (const T*)c->ua(), c->geo,
                            (T)c->p.mobility, (T)kap, ntx, nty);
       } else {
-        hipLaunchKernelGGL((k_muscl<DIM, T>), rows(c), dim3(NT), 0, c->stream, (const T*)c->phi(),
+        hipLaunchKernelGGL((k_muscl<DIM, QH, T>), rows(c), dim3(NT), 0, c->stream, (const T*)c->phi(),
                            (T*)c->phi_next(), (const T*)c->ua(), c->geo, (T)c->p.mobility, (T)kap);
       }
     }
@@ -488,7 +494,7 @@ struct Engine {
         rc = c->fail(LBM_E_HIP, "host to device copy failed");
         break;
       }
-      hipLaunchKernelGGL((k_init<DIM, T, FS, GS>), rows(c), dim3(NT), 0, c->stream, (FS*)c->f(),
+      hipLaunchKernelGGL((k_init<DIM, QH, T, FS, GS>), rows(c), dim3(NT), 0, c->stream, (FS*)c->f(),
                          (GS*)c->g(), (const T*)c->phi(), (const T*)du, (const T*)dps, c->geo, physT(c));
       if (hipGetLastError() != hipSuccess || hipStreamSynchronize(c->stream) != hipSuccess)
         rc = c->fail(LBM_E_HIP, "initialisation kernel failed");
@@ -502,19 +508,19 @@ struct Engine {
                      double* go) {
     const long long B = (long long)bx * by * bz;
     double *df = nullptr, *dg = nullptr;
-    HIP_OR_FAIL(c, hipMalloc(&df, sizeof(double) * Hydro<DIM>::Q * B));
+    HIP_OR_FAIL(c, hipMalloc(&df, sizeof(double) * HydroQ<QH>::Q * B));
     if (hipMalloc(&dg, sizeof(double) * Phase<DIM>::Q * B) != hipSuccess) {
       (void)hipFree(df);
       return c->fail(LBM_E_OOM, "temporary allocation failed");
     }
     const int par = (int)(c->step & 1);
-    auto k = par == 0 ? k_getpop<DIM, 0, T, FS, GS> : k_getpop<DIM, 1, T, FS, GS>;
+    auto k = par == 0 ? k_getpop<DIM, QH, 0, T, FS, GS> : k_getpop<DIM, QH, 1, T, FS, GS>;
     hipLaunchKernelGGL(k, dim3((unsigned)((B + NT - 1) / NT)), dim3(NT), 0, c->stream,
                        (const FS*)c->f(), (const GS*)c->g(), c->geo, physT(c), x0, y0, z0, bx, by, bz,
                        df, dg);
     int rc = LBM_OK;
     if (hipStreamSynchronize(c->stream) != hipSuccess ||
-        (fo && hipMemcpy(fo, df, sizeof(double) * Hydro<DIM>::Q * B, hipMemcpyDeviceToHost)) ||
+        (fo && hipMemcpy(fo, df, sizeof(double) * HydroQ<QH>::Q * B, hipMemcpyDeviceToHost)) ||
         (go && hipMemcpy(go, dg, sizeof(double) * Phase<DIM>::Q * B, hipMemcpyDeviceToHost)))
       rc = c->fail(LBM_E_HIP, "population read-back failed");
     (void)hipFree(df);
@@ -525,17 +531,17 @@ struct Engine {
   static int set_pop(lbm_ctx* c, const double* fi, const double* gi) {
     const long long N = c->L.N;
     double *df = nullptr, *dg = nullptr;
-    HIP_OR_FAIL(c, hipMalloc(&df, sizeof(double) * Hydro<DIM>::Q * N));
+    HIP_OR_FAIL(c, hipMalloc(&df, sizeof(double) * HydroQ<QH>::Q * N));
     if (hipMalloc(&dg, sizeof(double) * Phase<DIM>::Q * N) != hipSuccess) {
       (void)hipFree(df);
       return c->fail(LBM_E_OOM, "temporary allocation failed");
     }
     int rc = LBM_OK;
-    if (hipMemcpy(df, fi, sizeof(double) * Hydro<DIM>::Q * N, hipMemcpyHostToDevice) ||
+    if (hipMemcpy(df, fi, sizeof(double) * HydroQ<QH>::Q * N, hipMemcpyHostToDevice) ||
         hipMemcpy(dg, gi, sizeof(double) * Phase<DIM>::Q * N, hipMemcpyHostToDevice)) {
       rc = c->fail(LBM_E_HIP, "host to device copy failed");
     } else {
-      hipLaunchKernelGGL((k_setpop<DIM, T, FS, GS>), dim3((unsigned)((N + NT - 1) / NT)), dim3(NT), 0,
+      hipLaunchKernelGGL((k_setpop<DIM, QH, T, FS, GS>), dim3((unsigned)((N + NT - 1) / NT)), dim3(NT), 0,
                          c->stream, (FS*)c->f(), (GS*)c->g(), c->geo, physT(c), df, dg);
       if (hipStreamSynchronize(c->stream) != hipSuccess) rc = c->fail(LBM_E_HIP, "set kernel failed");
     }
@@ -604,12 +610,12 @@ struct Engine {
 
   static void batch_launch(hipStream_t st, const JobT* dj, int nj, int blocks, int s, bool o32) {
     hipLaunchKernelGGL((k_phi_multi<DIM, T, FS, GS>), dim3((unsigned)blocks), dim3(NT), 0, st, dj, nj, s);
-    hipLaunchKernelGGL((k_nci_multi<DIM, T, FS, GS>), dim3(NCI_GRID), dim3(NT_NCI), 0, st, dj, nj, s);
+    hipLaunchKernelGGL((k_nci_multi<DIM, QH, T, FS, GS>), dim3(NCI_GRID), dim3(NT_NCI), 0, st, dj, nj, s);
     if (o32)
-      hipLaunchKernelGGL((k_collide_multi<DIM, T, FS, GS, true>), dim3((unsigned)blocks), dim3(NT), 0, st,
+      hipLaunchKernelGGL((k_collide_multi<DIM, QH, T, FS, GS, true>), dim3((unsigned)blocks), dim3(NT), 0, st,
                          dj, nj, s);
     else
-      hipLaunchKernelGGL((k_collide_multi<DIM, T, FS, GS, false>), dim3((unsigned)blocks), dim3(NT), 0,
+      hipLaunchKernelGGL((k_collide_multi<DIM, QH, T, FS, GS, false>), dim3((unsigned)blocks), dim3(NT), 0,
                          st, dj, nj, s);
   }
 
@@ -702,19 +708,21 @@ struct Engine {
   }
 };
 
-// Dispatch a functor over the (dimension, precision) combinations that are built.
+// Dispatch a functor over the (lattice, precision) combinations that are built.
+template <int DIM, int QH, typename Fn>
+int dispatch_prec(int pr, Fn&& fn) {
+  if (pr == LBM_FP64) return fn(Engine<DIM, QH, double, double, double>{});
+  if (pr == LBM_FP32) return fn(Engine<DIM, QH, float, float, float>{});
+  if (pr == LBM_FP32_F16STORE) return fn(Engine<DIM, QH, float, __half, float>{});
+  if (pr == LBM_FP32_BF16STORE) return fn(Engine<DIM, QH, float, __hip_bfloat16, float>{});
+  return LBM_E_UNSUPPORTED;
+}
 template <typename Fn>
 int dispatch(const lbm_ctx* c, Fn&& fn) {
-  const int d = c->p.dim, pr = c->p.precision;
-  if (d == 2 && pr == LBM_FP64) return fn(Engine<2, double, double, double>{});
-  if (d == 2 && pr == LBM_FP32) return fn(Engine<2, float, float, float>{});
-  if (d == 2 && pr == LBM_FP32_F16STORE) return fn(Engine<2, float, __half, float>{});
-  if (d == 2 && pr == LBM_FP32_BF16STORE) return fn(Engine<2, float, __hip_bfloat16, float>{});
-  if (d == 3 && pr == LBM_FP64) return fn(Engine<3, double, double, double>{});
-  if (d == 3 && pr == LBM_FP32) return fn(Engine<3, float, float, float>{});
-  if (d == 3 && pr == LBM_FP32_F16STORE) return fn(Engine<3, float, __half, float>{});
-  if (d == 3 && pr == LBM_FP32_BF16STORE) return fn(Engine<3, float, __hip_bfloat16, float>{});
-  return LBM_E_UNSUPPORTED;
+  const int pr = c->p.precision;
+  if (c->p.dim == 2) return dispatch_prec<2, 9>(pr, fn);
+  if (q_hydro(&c->p) == 27) return dispatch_prec<3, 27>(pr, fn);
+  return dispatch_prec<3, 19>(pr, fn);
 }
 
 void reset_nci_state(lbm_ctx* c) {
@@ -992,10 +1000,15 @@ int lbm_diagnostics(lbm_ctx* c, lbm_diag* out) {
 
 int lbm_lattice(int dim, int which, int* c) {
   if (dim != 2 && dim != 3) return LBM_E_INVALID;
-  const int q = which == 0 ? q_hydro(dim) : q_phase(dim);
+  if (which < 0 || which > 2 || (which == 2 && dim != 3)) return LBM_E_INVALID;
+  const int q = which == 0 ? q_hydro(dim) : (which == 1 ? q_phase(dim) : 27);
   if (c) {
     for (int i = 0; i < q; ++i) {
-      if (dim == 2) {
+      if (which == 2) {
+        c[3 * i] = HydroQ<27>::cx[i];
+        c[3 * i + 1] = HydroQ<27>::cy[i];
+        c[3 * i + 2] = HydroQ<27>::cz[i];
+      } else if (dim == 2) {
         c[3 * i] = Hydro<2>::cx[i];
         c[3 * i + 1] = Hydro<2>::cy[i];
         c[3 * i + 2] = 0;
@@ -1147,8 +1160,9 @@ int lbm_batch_step(lbm_ctx* const* ctxs, int count, int n) {
     if (!c->initialised) return c0->fail(LBM_E_STATE, "batch holds an uninitialised context");
     if (c->fd())
       return c0->fail(LBM_E_UNSUPPORTED, "batches step the lattice Boltzmann phase field only (cac_solver 0)");
-    if (c->dev != c0->dev || c->p.dim != c0->p.dim || c->p.precision != c0->p.precision)
-      return c0->fail(LBM_E_INVALID, "batch contexts must share device, dimension and precision");
+    if (c->dev != c0->dev || c->p.dim != c0->p.dim || c->p.precision != c0->p.precision ||
+        q_hydro(&c->p) != q_hydro(&c0->p))
+      return c0->fail(LBM_E_INVALID, "batch contexts must share device, lattice and precision");
     for (int j = 0; j < i; ++j)
       if (ctxs[j] == c) return c0->fail(LBM_E_INVALID, "context listed twice in batch");
   }

@@ -39,11 +39,14 @@ def test_workspace_bytes_model():
     # the finite-difference phase field adds a second phi plane and the u, a planes
     bfd = L.lbm_workspace_bytes(p.replace(cac_solver=1))
     assert 4 * n * (1 + 6) <= bfd - b < 4 * n * (1 + 6) * 1.02
+    # D3Q27 stores 8 more hydrodynamic populations
+    assert L.lbm_workspace_bytes(p.replace(hydro_q=27)) - b == 4 * n * 8
 
 
 @pytest.mark.parametrize("bad", [dict(dim=4), dict(nx=0), dict(tau=0.5), dict(nci_window=5),
                                  dict(eps_q=0.2), dict(rep_orient=2), dict(precision="fp8"),
-                                 dict(cac_solver=2)])
+                                 dict(cac_solver=2), dict(dim=3, nz=8, hydro_q=15),
+                                 dict(hydro_q=27)])
 def test_invalid_params_rejected(bad):
     kw = dict(dim=2, nx=32, ny=32, nz=1)
     kw.update(bad)
@@ -55,7 +58,7 @@ def test_invalid_params_rejected(bad):
 
 
 def test_lattice_orders():
-    for dim, which, q in ((2, 0, 9), (2, 1, 9), (3, 0, 19), (3, 1, 7)):
+    for dim, which, q in ((2, 0, 9), (2, 1, 9), (3, 0, 19), (3, 1, 7), (3, 2, 27)):
         c = L.lbm_lattice(dim, which)
         assert c.shape == (q, 3) and (c[0] == 0).all()
         # opposite pairs (2k-1, 2k)
