@@ -805,6 +805,15 @@ int oracle_set_populations(oracle_state* s, const double* f, const double* g) {
   return 0;
 }
 
+/* Test knob: the reference density of the buoyancy force, F_ext = (rho - rho_mean) g,
+ * is the box mean at initialisation; a sub-box cut from a larger periodic box takes
+ * the larger box's value instead. */
+int oracle_set_rho_mean(oracle_state* s, double rho_mean) {
+  if (!s) return -1;
+  s->rho_mean = rho_mean;
+  return 0;
+}
+
 int oracle_get_populations(const oracle_state* s, double* f, double* g) {
   const long N = s->N;
   const int Q = s->LF.q, QG = s->LG.q;

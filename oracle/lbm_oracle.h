@@ -66,6 +66,9 @@ int oracle_threads(void);
 int oracle_init_fields(oracle_state* s, const double* phi, const double* u, const double* pstar);
 /* Populations in natural layout (incoming populations at each cell), SoA [q][N]. */
 int oracle_set_populations(oracle_state* s, const double* f, const double* g);
+/* Test knob: override the reference density rho_mean of F_ext = (rho - rho_mean) g
+ * (by default the box mean at initialisation), for a sub-box of a larger box. */
+int oracle_set_rho_mean(oracle_state* s, double rho_mean);
 int oracle_get_populations(const oracle_state* s, double* f, double* g);
 int oracle_step(oracle_state* s, int n);
 long oracle_step_count(const oracle_state* s);

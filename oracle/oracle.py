@@ -61,6 +61,7 @@ def load():
     for name in ("oracle_init_fields",):
         getattr(lib, name).argtypes = [vp, dp, dp, dp]
     lib.oracle_set_populations.argtypes = [vp, dp, dp]
+    lib.oracle_set_rho_mean.argtypes = [vp, C.c_double]
     lib.oracle_get_populations.argtypes = [vp, dp, dp]
     lib.oracle_step.argtypes = [vp, C.c_int]
     lib.oracle_step_count.restype = C.c_long
@@ -170,6 +171,10 @@ class Oracle:
         g = np.ascontiguousarray(g, dtype=np.float64).reshape(-1)
         assert f.size == self.qf * self.N and g.size == self.qg * self.N
         self.lib.oracle_set_populations(self.h, _dptr(f), _dptr(g))
+
+    def set_rho_mean(self, rho_mean: float):
+        """Reference density of the buoyancy force for a sub-box of a larger box."""
+        self.lib.oracle_set_rho_mean(self.h, float(rho_mean))
 
     def get_populations(self):
         f = np.zeros(self.qf * self.N)
