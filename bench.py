@@ -156,6 +156,8 @@ def main():
     ap.add_argument("--gap", type=float, default=3.0)
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp16", "bf16", "fp64"])
     ap.add_argument("--diag", type=int, default=100)
+    ap.add_argument("--swarm-stats", action="store_true",
+                    help="also time the swarm statistics (curvature histogram, component volumes) once")
     ap.add_argument("--hydro-q", type=int, default=19, choices=[19, 27],
                     help="3D hydrodynamic lattice: D3Q19 or the paper's D3Q27")
     ap.add_argument("--phase-field", default="lbm", choices=["lbm", "muscl"],
@@ -253,6 +255,17 @@ def main():
     achieved = bytes_launch / avg_s / 1e9
     traffic = traffic_from_profile(args)
     diag = lat.diagnostics()
+    stats = None
+    if args.swarm_stats:
+        from paper_2603_17481_amd import swarmstats as SS
+        lat.curvature_histogram(SS.DEFAULT_Q_BAND, 0.0, 0.4, 80)   # first call: code objects, allocation
+        t0 = time.perf_counter()
+        counts = lat.curvature_histogram(SS.DEFAULT_Q_BAND, 0.0, 0.4, 80)
+        t1 = time.perf_counter()
+        vols = lat.component_volumes()
+        t2 = time.perf_counter()
+        stats = {"curvature_histogram_ms": round((t1 - t0) * 1e3, 2), "component_volumes_ms": round((t2 - t1) * 1e3, 2),
+                 "band_cells": int(counts.sum()), "components": int(len(vols))}
     out = {
         "metric": METRIC,
         "value": round(mlups, 1),
@@ -276,6 +289,7 @@ def main():
                      "step_frac": round(step_bytes * N / (ms_step / 1e3) / 1e9 / PEAK_HBM_GBS, 4)},
         "kernel_ms_per_launch": {k: round(v[0] / max(v[1], 1), 4) for k, v in kt.items()},
         "copy_gbs": round(copy_gbs, 1),
+        **({"swarm_stats": stats} if stats else {}),
         "state": {"step": diag["step"], "n_bubbles": diag["n_droplets"], "nci_active": diag["nci_active"],
                   "finite": diag["finite"], "mass_phi": diag["mass_phi"]},
     }

@@ -170,6 +170,28 @@ int lbm_diagnostics(lbm_ctx* ctx, lbm_diag* out);
  * at most max entries (the last 64 are kept).  Returns the count or <0. */
 int lbm_diag_history(lbm_ctx* ctx, lbm_diag* out, int max);
 
+/* Swarm statistics of the current state (the curvature and equivalent-diameter
+ * PDFs of the bubble-swarm section; not part of the coupled step).  Both
+ * synchronise and allocate temporary device memory.
+ *
+ * lbm_curvature_histogram: the interfacial mean curvature kappa = div n
+ * (Eq. kappa_radius; 2/R on a sphere of radius R), n the outward unit normal
+ * of the dispersed phase (grad phi / (|grad phi| + eps_n) for bubbles, its
+ * negative for droplets) and div the isotropic divergence of the hydrodynamic
+ * lattice, at the interface cells q = phi^(1 - phi^) >= q_band (phi^ = phi
+ * clamped to [0, 1]; 0 < q_band <= 1/4).  counts (nbins + 2 longs, 1 <= nbins
+ * <= 4096): [0] kappa < kmin, [nbins + 1] kappa >= kmax, [1 + b] the b-th of
+ * nbins equal bins of [kmin, kmax); the bin is taken in FP64 from kappa.
+ *
+ * lbm_component_volumes: cell counts of the connected components (8- / 26-
+ * connected, periodic) of the dispersed set, largest first; at most max are
+ * written to volumes, *count receives the number of components (droplets or
+ * bubbles).  Equivalent diameters follow as (6 V / pi)^(1/3) (3D) or
+ * (4 V / pi)^(1/2) (2D).  Errors: LBM_E_INVALID, LBM_E_STATE, LBM_E_OOM,
+ * LBM_E_HIP. */
+int lbm_curvature_histogram(lbm_ctx* ctx, double q_band, double kmin, double kmax, int nbins, long* counts);
+int lbm_component_volumes(lbm_ctx* ctx, long* volumes, long max, long* count);
+
 /* Per-kernel timing with HIP events recorded on the context's stream around
  * every launch lbm_step makes (0 phi moment and interface flags, 1
  * near-contact, 2 collide + stream, 3 diagnostics, 4 finite-difference phase

@@ -882,7 +882,10 @@ int oracle_get_nci(oracle_state* s, int* chi, int* partner, double* J) {
 
 /* Breadth-first flood fill of the dispersed set with 8- (2D) or 26- (3D)
  * connectivity on the periodic lattice. */
-long oracle_count_components(int dim, int nx, int ny, int nz, const double* phi, int dispersed) {
+/* Breadth-first search over the dispersed set; sizes[k] (when given, up to
+ * max entries) receives the cell count of the k-th component found. */
+long oracle_component_sizes(int dim, int nx, int ny, int nz, const double* phi, int dispersed, long* sizes,
+                            long max) {
   long NZ = (dim == 2) ? 1 : nz;
   long N = (long)nx * ny * NZ;
   unsigned char* mark = (unsigned char*)calloc((size_t)N, 1);
@@ -910,10 +913,15 @@ long oracle_count_components(int dim, int nx, int ny, int nz, const double* phi,
             queue[tail++] = j;
           }
     }
+    if (sizes && count <= max) sizes[count - 1] = tail;
   }
   free(mark);
   free(queue);
   return count;
+}
+
+long oracle_count_components(int dim, int nx, int ny, int nz, const double* phi, int dispersed) {
+  return oracle_component_sizes(dim, nx, ny, nz, phi, dispersed, NULL, 0);
 }
 
 int oracle_diagnostics(oracle_state* s, oracle_diag* out) {

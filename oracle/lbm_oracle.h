@@ -97,6 +97,10 @@ double oracle_film_thickness(const oracle_params* p, double q_pair);
 double oracle_thickness_weight(const oracle_params* p, double h);
 /* Connected components of the dispersed set (8-/26-connectivity, periodic). */
 long oracle_count_components(int dim, int nx, int ny, int nz, const double* phi, int dispersed);
+/* The same search, also giving the cell count of each component (in the order found, at
+ * most max of them). */
+long oracle_component_sizes(int dim, int nx, int ny, int nz, const double* phi, int dispersed, long* sizes,
+                            long max);
 
 #ifdef __cplusplus
 }

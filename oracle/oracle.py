@@ -82,6 +82,9 @@ def load():
     lib.oracle_thickness_weight.argtypes = [C.POINTER(_Params), C.c_double]
     lib.oracle_count_components.restype = C.c_long
     lib.oracle_count_components.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, dp, C.c_int]
+    lib.oracle_component_sizes.restype = C.c_long
+    lib.oracle_component_sizes.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, dp, C.c_int,
+                                           C.POINTER(C.c_long), C.c_long]
     lib.oracle_lattice.argtypes = [C.c_int, ip, ip, dp, dp]
     _lib = lib
     return lib
@@ -311,3 +314,52 @@ def count_components(params, phi, dispersed):
     a = np.ascontiguousarray(phi, dtype=np.float64).reshape(-1)
     nz = params.nz if params.dim == 3 else 1
     return int(lib.oracle_count_components(params.dim, params.nx, params.ny, nz, _dptr(a), dispersed))
+
+
+def component_sizes(params, phi, dispersed):
+    """Cell counts of the connected components (8- / 26-connected, periodic) of the
+    dispersed set {phi > 1/2} (dispersed = 1) or {phi < 1/2} (0), largest first."""
+    lib = load()
+    a = np.ascontiguousarray(phi, dtype=np.float64).reshape(-1)
+    nz = params.nz if params.dim == 3 else 1
+    cap = a.size
+    out = np.zeros(cap, dtype=np.int64)
+    n = int(lib.oracle_component_sizes(params.dim, params.nx, params.ny, nz, _dptr(a), dispersed,
+                                       out.ctypes.data_as(C.POINTER(C.c_long)), cap))
+    return np.sort(out[:n])[::-1]
+
+
+def mean_curvature(params, n, dispersed):
+    """Mean curvature kappa = div n_out (Eq. kappa_radius) of the interface of the
+    dispersed phase, n_out its outward unit normal (n from Oracle.gradients(): grad phi
+    over (|grad phi| + eps_n), so n_out = n for bubbles and -n for droplets), with the
+    isotropic divergence (1/cs^2) sum_i w_i c_i . n_out(x + c_i) on the hydrodynamic
+    lattice.  Written out literally with periodic shifts."""
+    dim = params.dim
+    kind = 0 if dim == 2 else (3 if getattr(params, "hydro_q", 19) == 27 else 1)
+    c, w, cs2 = lattice(kind)
+    sgn = 1.0 if dispersed == 0 else -1.0
+    kappa = np.zeros(params.shape)
+    axes = tuple(range(dim))[::-1]      # array axes of x, y, z (arrays are [z][y][x])
+    for i in range(len(w)):
+        shifted = 0.0
+        for a in range(dim):
+            if c[i][a] == 0:
+                continue
+            # n_out(x + c_i): roll by -c_i along every axis
+            v = n[a]
+            for b in range(dim):
+                if c[i][b]:
+                    v = np.roll(v, -int(c[i][b]), axis=axes[b])
+            shifted = shifted + c[i][a] * v
+        kappa += w[i] * shifted
+    return sgn * kappa / cs2
+
+
+def histogram_bins(values, lo, hi, nbins):
+    """Bin index of each value: 0 below lo, nbins + 1 at or above hi, else
+    1 + floor((v - lo) / (hi - lo) * nbins) (at most nbins)."""
+    v = np.asarray(values, dtype=np.float64)
+    b = 1 + np.minimum(nbins - 1, np.floor((v - lo) / (hi - lo) * nbins).astype(np.int64))
+    b = np.where(v < lo, 0, b)
+    return np.where(v >= hi, nbins + 1, b)

@@ -17,6 +17,7 @@
 
 #include "../../include/lbm.h"
 #include "kernels.hpp"
+#include "stats.hpp"
 
 using namespace lbm;
 
@@ -565,6 +566,72 @@ struct Engine {
     return rc;
   }
 
+  // Swarm statistics of the current state (stats.hpp).
+  static int curvature_hist(lbm_ctx* c, double q_band, double kmin, double kmax, int nbins, long* out) {
+    const int par = (int)(c->step & 1);
+    phi_pass(c, par);
+    T* n = nullptr;
+    unsigned long long* dc = nullptr;
+    HIP_OR_FAIL(c, hipMalloc(&n, sizeof(T) * DIM * c->L.S));
+    if (hipMalloc(&dc, sizeof(unsigned long long) * (nbins + 2)) != hipSuccess) {
+      (void)hipFree(n);
+      return c->fail(LBM_E_OOM, "temporary allocation failed");
+    }
+    int rc = LBM_OK;
+    std::vector<unsigned long long> h((size_t)nbins + 2);
+    const T sgn = c->dispersed ? (T)-1 : (T)1;
+    if (hipMemsetAsync(dc, 0, sizeof(unsigned long long) * (nbins + 2), c->stream) != hipSuccess) {
+      rc = c->fail(LBM_E_HIP, "memset failed");
+    } else {
+      hipLaunchKernelGGL((k_normal<DIM, QH, T>), rows(c), dim3(NT), 0, c->stream, (const T*)c->phi(), n, c->geo,
+                         sgn, (T)c->p.eps_n);
+      hipLaunchKernelGGL((k_curv_hist<DIM, QH, T>), rows(c), dim3(NT), 0, c->stream, (const T*)c->phi(),
+                         (const T*)n, c->geo, (T)q_band, kmin, kmax, nbins, dc);
+      if (hipGetLastError() != hipSuccess || hipStreamSynchronize(c->stream) != hipSuccess ||
+          hipMemcpy(h.data(), dc, sizeof(unsigned long long) * (nbins + 2), hipMemcpyDeviceToHost) != hipSuccess)
+        rc = c->fail(LBM_E_HIP, "curvature histogram failed");
+    }
+    for (int b = 0; rc == LBM_OK && b < nbins + 2; ++b) out[b] = (long)h[b];
+    (void)hipFree(n);
+    (void)hipFree(dc);
+    return rc;
+  }
+
+  static int component_volumes(lbm_ctx* c, long* out, long max, long* count) {
+    const int par = (int)(c->step & 1);
+    phi_pass(c, par);
+    const long long N = c->L.N;
+    const unsigned cap = (unsigned)std::min<long>(max, (long)N);
+    unsigned *vol = nullptr, *lst = nullptr;
+    HIP_OR_FAIL(c, hipMalloc(&vol, sizeof(unsigned) * (N + 1 + (long long)cap)));
+    lst = vol + N + 1;   // [N] is the component counter, then the list
+    int rc = LBM_OK;
+    unsigned n = 0;
+    std::vector<unsigned> h(cap);
+    if (hipMemsetAsync(vol, 0, sizeof(unsigned) * (N + 1), c->stream) != hipSuccess) {
+      rc = c->fail(LBM_E_HIP, "memset failed");
+    } else {
+      hipLaunchKernelGGL((k_cc_init<DIM, T>), rows(c), dim3(NT), 0, c->stream, (const T*)c->phi(), c->geo,
+                         c->dispersed, c->lab());
+      hipLaunchKernelGGL((k_cc_merge<DIM>), rows(c), dim3(NT), 0, c->stream, c->geo, c->lab());
+      hipLaunchKernelGGL(k_cc_volume, rows(c), dim3(NT), 0, c->stream, c->geo, (const unsigned*)c->lab(), vol);
+      hipLaunchKernelGGL(k_cc_list, rows(c), dim3(NT), 0, c->stream, c->geo, (const unsigned*)c->lab(),
+                         (const unsigned*)vol, lst, cap, vol + N);
+      if (hipGetLastError() != hipSuccess || hipStreamSynchronize(c->stream) != hipSuccess ||
+          hipMemcpy(&n, vol + N, sizeof(unsigned), hipMemcpyDeviceToHost) != hipSuccess ||
+          (cap && hipMemcpy(h.data(), lst, sizeof(unsigned) * cap, hipMemcpyDeviceToHost) != hipSuccess))
+        rc = c->fail(LBM_E_HIP, "component volumes failed");
+    }
+    if (rc == LBM_OK) {
+      const unsigned m = std::min(n, cap);
+      std::sort(h.begin(), h.begin() + m, [](unsigned a, unsigned b) { return a > b; });
+      for (unsigned k = 0; k < m; ++k) out[k] = (long)h[k];
+      *count = (long)n;
+    }
+    (void)hipFree(vol);
+    return rc;
+  }
+
   static int get_phi(lbm_ctx* c, double* out) {
     const int par = (int)(c->step & 1);
     phi_pass(c, par);
@@ -961,6 +1028,21 @@ int lbm_get_phi(lbm_ctx* c, double* out) {
   NEED_INIT(c);
   if (!out) return c->fail(LBM_E_INVALID, "null output");
   return dispatch(c, [&](auto E) { return decltype(E)::get_phi(c, out); });
+}
+
+int lbm_curvature_histogram(lbm_ctx* c, double q_band, double kmin, double kmax, int nbins, long* counts) {
+  NEED_INIT(c);
+  if (!counts) return c->fail(LBM_E_INVALID, "null output");
+  if (nbins < 1 || nbins > STATS_MAX_BINS) return c->fail(LBM_E_INVALID, "nbins must be in [1, 4096]");
+  if (!(kmax > kmin) || !(q_band > 0.0) || !(q_band <= 0.25))
+    return c->fail(LBM_E_INVALID, "need kmax > kmin and 0 < q_band <= 1/4");
+  return dispatch(c, [&](auto E) { return decltype(E)::curvature_hist(c, q_band, kmin, kmax, nbins, counts); });
+}
+
+int lbm_component_volumes(lbm_ctx* c, long* volumes, long max, long* count) {
+  NEED_INIT(c);
+  if (!count || max < 0 || (max > 0 && !volumes)) return c->fail(LBM_E_INVALID, "bad output");
+  return dispatch(c, [&](auto E) { return decltype(E)::component_volumes(c, volumes, max, count); });
 }
 
 int lbm_get_pstar(lbm_ctx* c, double* out) {

@@ -101,6 +101,9 @@ def load():
     lib.lbm_batch_step.argtypes = [C.POINTER(vp), C.c_int, C.c_int]
     lib.lbm_timing.argtypes = [vp, C.c_int]
     lib.lbm_kernel_times.argtypes = [vp, dp, C.POINTER(C.c_long)]
+    lp = C.POINTER(C.c_long)
+    lib.lbm_curvature_histogram.argtypes = [vp, C.c_double, C.c_double, C.c_double, C.c_int, lp]
+    lib.lbm_component_volumes.argtypes = [vp, lp, C.c_long, lp]
     _lib = lib
     return lib
 
@@ -294,6 +297,23 @@ class Lattice:
 
     def timing(self, enable: bool = True):
         self._check(self.lib.lbm_timing(self.h, 1 if enable else 0))
+
+    def curvature_histogram(self, q_band: float, kmin: float, kmax: float, nbins: int) -> np.ndarray:
+        """Counts of the interfacial mean curvature: [below kmin, nbins bins, at or above kmax]."""
+        out = np.zeros(nbins + 2, dtype=np.int64)
+        self._check(self.lib.lbm_curvature_histogram(self.h, float(q_band), float(kmin), float(kmax), int(nbins),
+                                                     out.ctypes.data_as(C.POINTER(C.c_long))))
+        return out
+
+    def component_volumes(self, max_count: int = 1 << 20) -> np.ndarray:
+        """Cell counts of the dispersed components, largest first."""
+        out = np.zeros(max_count, dtype=np.int64)
+        n = C.c_long()
+        self._check(self.lib.lbm_component_volumes(self.h, out.ctypes.data_as(C.POINTER(C.c_long)), int(max_count),
+                                                   C.byref(n)))
+        if n.value > max_count:
+            raise LBMError(-1, f"{n.value} components, more than max_count = {max_count}")
+        return out[: n.value].copy()
 
     def kernel_times(self):
         """{kernel: (total_ms, launches)} since the last call (synchronises)."""

@@ -828,3 +828,56 @@ def test_muscl_slab_relaxes_to_tanh_profile():
     wfit, half = _fit_slab(o.phi()[0], N, Wd)
     assert abs(wfit - Wd) <= 0.05 * Wd, wfit
     assert abs(half - N / 4) <= 0.05 * N / 4
+
+
+# ---------------------------------------------------------------------------
+# Swarm statistics (the curvature and equivalent-diameter PDFs of the swarm
+# section, Eq. kappa_radius)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("dim,q,R", [(2, 9, 16.0), (3, 19, 12.0), (3, 27, 12.0)])
+@pytest.mark.parametrize("bubble", [True, False])
+def test_mean_curvature_of_a_sphere(dim, q, R, bubble):
+    """kappa = div n_out = (dim - 1) / R on a sphere (2/R in 3D), for a bubble (phi = 0
+    inside, n_out = grad phi / |grad phi|) and a droplet (phi = 1 inside, the opposite
+    sign): the mean over the interface band is within 1 %, and every band cell lies
+    within the curvature of the band's inner and outer radii."""
+    n = 48 if dim == 3 else 96
+    p = W.Params(dim=dim, nx=n, ny=n, nz=n if dim == 3 else 1, width=4.0, a_rep=0.0,
+                 hydro_q=q if dim == 3 else 19)
+    st = W.spheres_state(p, [W.Sphere(tuple([n / 2 - 0.3] * 3), R)], not bubble, "sphere")
+    o = O.Oracle(p)
+    o.init_fields(st.phi)
+    g, lap, nn, qq, mu = o.gradients()
+    k = O.mean_curvature(p, nn, 0 if bubble else 1)
+    ph = np.clip(st.phi, 0, 1)
+    band = ph * (1 - ph) >= 3 / 16
+    assert band.sum() > 100
+    assert abs(k[band].mean() / ((dim - 1) / R) - 1) < 1e-2
+    # band radii: phi = 1/4 .. 3/4 on the tanh profile lies within W ln(3)/4 of R
+    d = 4.0 * math.log(3.0) / 4.0 + 0.9
+    assert k[band].min() > (dim - 1) / (R + d) * 0.9 and k[band].max() < (dim - 1) / (R - d) * 1.1
+
+
+def test_component_sizes_and_bins():
+    """Cell counts of separated bubbles equal the direct count of set cells around each
+    centre; the BFS count equals their number; the bin rule puts edges in the upper bin."""
+    p = W.Params(dim=3, nx=48, ny=40, nz=36, width=4.0, a_rep=0.0)
+    sph = [W.Sphere((10.2, 10.1, 9.7), 6.0), W.Sphere((30.4, 12.2, 20.3), 8.5),
+           W.Sphere((20.1, 30.3, 26.6), 4.5), W.Sphere((45.2, 35.3, 2.1), 5.0)]   # the last wraps
+    st = W.spheres_state(p, sph, False, "bubbles")
+    sizes = O.component_sizes(p, st.phi, 0)
+    z, y, x = np.meshgrid(np.arange(36), np.arange(40), np.arange(48), indexing="ij")
+    direct = []
+    for s in sph:
+        dx = (x - s.center[0] + 24) % 48 - 24
+        dy = (y - s.center[1] + 20) % 40 - 20
+        dz = (z - s.center[2] + 18) % 36 - 18
+        near = dx * dx + dy * dy + dz * dz < (s.radius + 3) ** 2
+        direct.append(int(((st.phi < 0.5) & near).sum()))
+    assert list(sizes) == sorted(direct, reverse=True)
+    assert len(sizes) == O.count_components(p, st.phi, 0) == 4
+    for s, v in zip(sorted(sph, key=lambda s: -s.radius), sizes):
+        assert abs(v / (4 / 3 * math.pi * s.radius ** 3) - 1) < 0.06
+    b = O.histogram_bins([-1.0, 0.0, 0.25, 0.9999, 1.0, 2.0], 0.0, 1.0, 4)
+    assert list(b) == [0, 1, 2, 4, 5, 5]
