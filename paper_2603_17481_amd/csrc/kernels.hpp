@@ -28,9 +28,8 @@
 
 namespace lbm {
 
-constexpr int BX = 64;   // cells along x per block (one wave)
-constexpr int BY = 4;    // rows per block
-constexpr int NT = BX * BY;
+constexpr int NT = 256;   // threads of the cell-wise kernels: a block covers NT cells of one
+                          // z plane, 2^bxs along x (Geo::bxs) by NT >> bxs rows
 constexpr int NT_NCI = 512;   // near-contact kernel: two blocks of 512 per CU fit its LDS
 constexpr int PHI_HALO = 4;   // window radius 3 + 1 for the normals
 constexpr int NQ_HALO = 3;    // window radius
@@ -49,6 +48,7 @@ struct Geo {
   int ntx, nty, ntz;     // near-contact tiles along x, y, z
   int rs;                // population chunks hold R = 2^rs rows ...
   int qc;                // ... i.e. qc = R nx cells per population
+  int bxs;               // cell-wise blocks are 2^bxs cells wide (6, 7 or 8)
 };
 
 struct Phys {
@@ -354,12 +354,15 @@ __device__ __forceinline__ int slab_block(const Geo& g) {
   return (k + 8 * (i / per)) * per + i % per;
 }
 
-// Cell of thread: block t of a domain covers BX x BY cells of one z plane.
+// Cell of thread: block t of a domain covers 2^bxs x (NT >> bxs) cells of one
+// z plane.  Rows of 256 cells (1 KB per population in FP32) stream 4.5 % faster
+// through the collide than 64 x 4 blocks at 512^3; narrow boxes use 64-wide
+// blocks so that few lanes idle.
 __device__ __forceinline__ void block_cell(int t, const Geo& geo, int& x, int& y, int& z) {
   const int bx = t % geo.nbx, r = t / geo.nbx, by = r % geo.nby;
   z = r / geo.nby;
-  x = bx * BX + (int)(threadIdx.x & (BX - 1));
-  y = by * BY + (int)(threadIdx.x / BX);
+  x = (bx << geo.bxs) + (int)(threadIdx.x & ((1u << geo.bxs) - 1u));
+  y = by * (NT >> geo.bxs) + (int)(threadIdx.x >> geo.bxs);
 }
 
 template <int DIM, int PAR, typename T, typename GS, bool GIVEN>
@@ -1517,9 +1520,8 @@ __global__ __launch_bounds__(NT) void k_init(FS* __restrict__ f, GS* __restrict_
                                              const T* __restrict__ psin, Geo geo, PhysT<T> pp) {
   using H = HydroQ<QH>;
   using P = Phase<DIM>;
-  const int t = swizzled_block();
-  const int bx = t % geo.nbx, r = t / geo.nbx, by = r % geo.nby, z = r / geo.nby;
-  const int x = bx * BX + (int)(threadIdx.x & (BX - 1)), y = by * BY + (int)(threadIdx.x / BX);
+  int x, y, z;
+  block_cell(swizzled_block(), geo, x, y, z);
   if (x >= geo.nx || y >= geo.ny) return;
   const Nbr nb(x, y, z, geo);
   const int idx = nb(0, 0, 0);

@@ -52,6 +52,7 @@ struct Layout {
   long long N, S;
   int nblk, ntiles, ttx, tty, ttz, ntx, nty, ntz;
   int rs, qc;   // population chunks: 2^rs rows, qc = nx 2^rs cells
+  int bxs;      // cell-wise blocks are 2^bxs cells wide
   size_t off_f, off_g, off_phi, off_J, off_flags, off_list, off_cnt, off_pa, off_pb, off_s1,
       off_red, off_lab, off_phi2, off_ua, total;
 };
@@ -91,6 +92,16 @@ bool valid_params(const lbm_params* p, std::string* why) {
   return true;
 }
 
+// Width of the cell-wise blocks: the widest of 256, 128, 64 cells that leaves
+// at most 1/8 of the lanes of a row idle (256 at nx = 512; 64 for narrow boxes).
+int block_shift(int nx) {
+  for (int s = 8; s > 6; --s) {
+    const int w = 1 << s;
+    if ((long long)((nx + w - 1) / w) * w * 8 <= (long long)nx * 9) return s;
+  }
+  return 6;
+}
+
 Layout make_layout(const lbm_params* p) {
   Layout L{};
   L.N = (long long)p->nx * p->ny * p->nz;
@@ -110,7 +121,9 @@ Layout make_layout(const lbm_params* p) {
     L.rs = std::min(std::max(0, 13 - lg), tz);
     L.qc = p->nx << L.rs;
   }
-  const int nbx = (p->nx + BX - 1) / BX, nby = (p->ny + BY - 1) / BY;
+  L.bxs = block_shift(p->nx);
+  const int bw = 1 << L.bxs, bh = NT >> L.bxs;
+  const int nbx = (p->nx + bw - 1) / bw, nby = (p->ny + bh - 1) / bh;
   L.nblk = nbx * nby * p->nz;
   tile_dims(p->dim, p->precision, &L.ttx, &L.tty, &L.ttz);
   L.ntx = (p->nx + L.ttx - 1) / L.ttx;
@@ -922,8 +935,9 @@ int lbm_create(const lbm_params* p, void* dev_workspace, size_t ws_bytes, void* 
   G.nx = p->nx;
   G.ny = p->ny;
   G.nz = p->nz;
-  G.nbx = (p->nx + BX - 1) / BX;
-  G.nby = (p->ny + BY - 1) / BY;
+  G.bxs = c->L.bxs;
+  G.nbx = (p->nx + (1 << G.bxs) - 1) >> G.bxs;
+  G.nby = (p->ny + (NT >> G.bxs) - 1) / (NT >> G.bxs);
   G.S = c->L.S;
   G.ntx = c->L.ntx;
   G.nty = c->L.nty;
