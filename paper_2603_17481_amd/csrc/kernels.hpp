@@ -103,17 +103,26 @@ __device__ __forceinline__ int wrapi(int i, int n) {
   return r < 0 ? r + n : r;
 }
 
+// Populations are touched once per step: their loads and stores carry the
+// nontemporal hint (streamed past the caches).  Together, at 512^3 FP32, they
+// take the collide from 5.54 to 5.33 ms (FP64 11.1 -> 10.9 ms); loads alone slow
+// it down, and the 16-bit stores are as fast without the hint.
+template <typename E>
+__device__ __forceinline__ E ld_nt(const E* p) { return __builtin_nontemporal_load(p); }
+template <typename E>
+__device__ __forceinline__ void st_nt(E* p, E v) { __builtin_nontemporal_store(v, p); }
+
 template <typename S>
 struct Store;
 template <>
 struct Store<double> {
-  __device__ static double ld(const double* p, double) { return *p; }
-  __device__ static void st(double* p, double v, double) { *p = v; }
+  __device__ static double ld(const double* p, double) { return ld_nt(p); }
+  __device__ static void st(double* p, double v, double) { st_nt(p, v); }
 };
 template <>
 struct Store<float> {
-  __device__ static float ld(const float* p, float) { return *p; }
-  __device__ static void st(float* p, float v, float) { *p = v; }
+  __device__ static float ld(const float* p, float) { return ld_nt(p); }
+  __device__ static void st(float* p, float v, float) { st_nt(p, v); }
 };
 template <>
 struct Store<__half> {
@@ -318,11 +327,11 @@ __device__ __forceinline__ void phi_cell(const GS* __restrict__ g, T* __restrict
     const PopNbr<const GS> pn(g, x, y, z, geo, P::Q);
     if constexpr (PAR == 0) {
 #pragma unroll
-      for (int i = 0; i < P::Q; ++i) acc += (double)*pn.template at<false>(i, 0, 0, 0);
+      for (int i = 0; i < P::Q; ++i) acc += (double)ld_nt(pn.template at<false>(i, 0, 0, 0));
     } else {
 #pragma unroll
       for (int i = 0; i < P::Q; ++i)
-        acc += (double)*pn.template at<false>(opp(i), -P::cx[i], -P::cy[i], -P::cz[i]);
+        acc += (double)ld_nt(pn.template at<false>(opp(i), -P::cx[i], -P::cy[i], -P::cz[i]));
     }
     s = (T)acc;
     phi[idx] = s;
@@ -990,12 +999,12 @@ __device__ __forceinline__ void collide_cell(const Planes<FS, GS>& pl, const T* 
     for (int k = 0; k < QG; ++k) {
       const GS* src = PAR == 0 ? pg.template at<OFF32>(k, 0, 0, 0)
                                : pg.template at<OFF32>(opp(k), -P::cx[k], -P::cy[k], -P::cz[k]);
-      gi[k] = (T)*src;
+      gi[k] = (T)ld_nt(src);
     }
     // geq - g is formed with the product unrounded: a rounded w_k (phi + c.j/cs^2)
     // (the D2Q9 weights are not powers of two) would bias the phase-field mass
     // of every step, like weights that do not sum to one.
-    *pg.template at<OFF32>(0, 0, 0, 0) = (GS)fmad(fmad(wt<P, T>(0), ph, -gi[0]), itp, gi[0]);
+    st_nt(pg.template at<OFF32>(0, 0, 0, 0), (GS)fmad(fmad(wt<P, T>(0), ph, -gi[0]), itp, gi[0]));
 #pragma unroll
     for (int k = 1; k < QG; k += 2) {
       const int cx = P::cx[k], cy = P::cy[k], cz = P::cz[k];
@@ -1004,11 +1013,11 @@ __device__ __forceinline__ void collide_cell(const Planes<FS, GS>& pl, const T* 
       const T ga = fmad(fmad(wk, ph + cj, -gi[k]), itp, gi[k]);
       const T gb = fmad(fmad(wk, ph - cj, -gi[k + 1]), itp, gi[k + 1]);
       if constexpr (PAR == 0) {
-        *pg.template at<OFF32>(k + 1, 0, 0, 0) = (GS)ga;
-        *pg.template at<OFF32>(k, 0, 0, 0) = (GS)gb;
+        st_nt(pg.template at<OFF32>(k + 1, 0, 0, 0), (GS)ga);
+        st_nt(pg.template at<OFF32>(k, 0, 0, 0), (GS)gb);
       } else {
-        *pg.template at<OFF32>(k, cx, cy, cz) = (GS)ga;
-        *pg.template at<OFF32>(k + 1, -cx, -cy, -cz) = (GS)gb;
+        st_nt(pg.template at<OFF32>(k, cx, cy, cz), (GS)ga);
+        st_nt(pg.template at<OFF32>(k + 1, -cx, -cy, -cz), (GS)gb);
       }
     }
     }
