@@ -343,7 +343,7 @@ __device__ __forceinline__ void phi_cell(const GS* __restrict__ g, T* __restrict
         acc += (double)ld_nt(pn.template at<false>(opp(i), -P::cx[i], -P::cy[i], -P::cz[i]));
     }
     s = (T)acc;
-    phi[idx] = s;
+    st_nt(phi + idx, s);   // read again by other kernels only
   }
   if (nci_on) {
     const T pc = s < (T)0 ? (T)0 : (s > (T)1 ? (T)1 : s);
@@ -1021,8 +1021,8 @@ __device__ __forceinline__ void collide_cell(const Planes<FS, GS>& pl, const T* 
       const T kn = ph * ((T)1 - ph) * inv_g;
 #pragma unroll
       for (int a = 0; a < DIM; ++a) {
-        uout[a * S + idx] = u[a];
-        uout[(DIM + a) * S + idx] = kn * gr[a];
+        st_nt(uout + a * S + idx, u[a]);
+        st_nt(uout + (DIM + a) * S + idx, kn * gr[a]);
       }
     } else {
     // ---- conservative Allen-Cahn populations: BGK towards
@@ -1413,7 +1413,7 @@ __global__ __launch_bounds__(MuslTile<T>::NT) void k_muscl3(const T* __restrict_
       const T div = (flux_difference<T>(ph, uv, 0) + flux_difference<T>(ph, uv, 1)) + (fzp - fzm);
       fzm = fzp;
       const T inc = muscl_increment<3, QH, T>(ph, av, div, mob, kap);
-      *(T*)((char*)(out + (long long)z * plane) + owno) = q2 + inc;
+      st_nt((T*)((char*)(out + (long long)z * plane) + owno), q2 + inc);
     }
     __syncthreads();
     const int tmp = sm;
