@@ -103,11 +103,11 @@ __device__ __forceinline__ int wrapi(int i, int n) {
   return r < 0 ? r + n : r;
 }
 
-// Populations are touched once per step: in the even AA parity their loads and
-// stores carry the nontemporal hint (streamed past the caches), which takes that
-// parity from about 5.5 to 4.6 ms at 512^3 FP32 (loads alone slow it down; the
-// 16-bit accesses are as fast without it).  Store<S>::ldh / sth are the hinted
-// forms, ld / st the plain ones.
+// Populations are touched once per step: their aligned loads and stores carry
+// the nontemporal hint (streamed past the caches), which takes the even AA
+// parity from about 5.5 to 4.6 ms at 512^3 FP32 and the FP16-storage collide
+// from 3.64 to 3.45 ms (hinted loads alone slow it down).  Store<S>::ldh / sth
+// are the hinted forms, ld / st the plain ones.
 template <typename E>
 __device__ __forceinline__ E ld_nt(const E* p) { return __builtin_nontemporal_load(p); }
 template <typename E>
@@ -133,15 +133,23 @@ template <>
 struct Store<__half> {
   __device__ static float ld(const __half* p, float off) { return __half2float(*p) + off; }
   __device__ static void st(__half* p, float v, float off) { *p = __float2half_rn(v - off); }
-  __device__ static float ldh(const __half* p, float off) { return ld(p, off); }
-  __device__ static void sth(__half* p, float v, float off) { st(p, v, off); }
+  __device__ static float ldh(const __half* p, float off) {
+    return __half2float(__ushort_as_half(ld_nt((const unsigned short*)p))) + off;
+  }
+  __device__ static void sth(__half* p, float v, float off) {
+    st_nt((unsigned short*)p, __half_as_ushort(__float2half_rn(v - off)));
+  }
 };
 template <>
 struct Store<__hip_bfloat16> {
   __device__ static float ld(const __hip_bfloat16* p, float off) { return __bfloat162float(*p) + off; }
   __device__ static void st(__hip_bfloat16* p, float v, float off) { *p = __float2bfloat16(v - off); }
-  __device__ static float ldh(const __hip_bfloat16* p, float off) { return ld(p, off); }
-  __device__ static void sth(__hip_bfloat16* p, float v, float off) { st(p, v, off); }
+  __device__ static float ldh(const __hip_bfloat16* p, float off) {
+    return __bfloat162float(__ushort_as_bfloat16(ld_nt((const unsigned short*)p))) + off;
+  }
+  __device__ static void sth(__hip_bfloat16* p, float v, float off) {
+    st_nt((unsigned short*)p, __bfloat16_as_ushort(__float2bfloat16(v - off)));
+  }
 };
 
 // Element e of a population plane.  With OFF32 the byte offset is formed in 32
