@@ -855,19 +855,27 @@ __device__ __forceinline__ double m_rcp(double a) { return 1.0 / a; }
 // the populations in place; MODE_STEP_DIAG also fills acc with the cell's
 // contributions to the FP64 diagnostics; MODE_DRY leaves the populations and
 // writes p*, rho, u, F to macro (when given).
-template <int DIM, int QH, int PAR, int MODE, typename T, typename FS, typename GS, bool OFF32>
+template <int DIM, int QH, int PAR, int MODE, typename T, typename FS, typename GS, bool OFF32,
+          bool XCH = false>
 __device__ __forceinline__ void collide_cell(const Planes<FS, GS>& pl, const T* __restrict__ phi,
                                              const T* __restrict__ J,
                                              const unsigned* __restrict__ flags, const Geo& geo,
                                              const PhysT<T>& pp, int nci_on, T* __restrict__ macro,
                                              T* __restrict__ uout, int x, int y, int z,
-                                             double acc[NPART]) {
+                                             double acc[NPART], FS* xf = nullptr,
+                                             GS* xg = nullptr) {
   using H = HydroQ<QH>;
   using P = Phase<DIM>;
   using TL = NciTile<DIM, T>;
   constexpr int Q = H::Q, QG = P::Q;
+  static_assert(!XCH || PAR == 1, "the row exchange serves the odd parity");
   const Nbr nb(x, y, z, geo);
   const unsigned idx = (unsigned)nb(0, 0, 0);
+  // XCH (k_collide_row): the odd parity's x-shifted populations of this cell's
+  // row are staged in LDS, xf / xg holding for x-shifted pair j (odd direction
+  // i) the row of slot i at (y + c_y, z + c_z) at 2 j nx and the row of slot
+  // i + 1 at (y - c_y, z - c_z) at (2 j + 1) nx.
+  const int xl = x == 0 ? geo.nx - 1 : x - 1, xr = x == geo.nx - 1 ? 0 : x + 1;
   // Population accesses stream past the caches (nontemporal) where they are
   // aligned: every access of the even parity, and the odd parity's accesses of
   // directions with c_x = 0.  The odd parity's accesses with c_x != 0 are
@@ -903,10 +911,20 @@ __device__ __forceinline__ void collide_cell(const Planes<FS, GS>& pl, const T* 
                                     : pf.template at<OFF32>(opp(i), 0, -H::cy[i], -H::cz[i]),
                            pp.fref[i]);
   }
+  if constexpr (XCH) {
 #pragma unroll
-  for (int i = 0; i < Q; ++i) {
-    if (PAR == 0 || H::cx[i] == 0) continue;
-    fi[i] = Store<FS>::ld(pf.template at<OFF32>(opp(i), -H::cx[i], -H::cy[i], -H::cz[i]), pp.fref[i]);
+    for (int i = 1; i < Q; i += 2) {
+      if (H::cx[i] == 0) continue;
+      const int j = xpair<H>(i), xm = H::cx[i] > 0 ? xl : xr, xp = H::cx[i] > 0 ? xr : xl;
+      fi[i] = Store<FS>::ld(xf + (2 * j + 1) * geo.nx + xm, pp.fref[i]);
+      fi[i + 1] = Store<FS>::ld(xf + 2 * j * geo.nx + xp, pp.fref[i]);
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      if (PAR == 0 || H::cx[i] == 0) continue;
+      fi[i] = Store<FS>::ld(pf.template at<OFF32>(opp(i), -H::cx[i], -H::cy[i], -H::cz[i]), pp.fref[i]);
+    }
   }
   T ps = fi[0], m[3] = {0, 0, 0}, M2[6] = {0, 0, 0, 0, 0, 0};  // xx yy zz xy xz yz
 #pragma unroll
@@ -1019,8 +1037,14 @@ __device__ __forceinline__ void collide_cell(const Planes<FS, GS>& pl, const T* 
       for (int i = 1; i < Q; i += 2) {
         const int cx = H::cx[i], cy = H::cy[i], cz = H::cz[i];
         if (cx == 0) continue;
-        Store<FS>::st(pf.template at<OFF32>(i, cx, cy, cz), fsx[i], pp.fref[i]);
-        Store<FS>::st(pf.template at<OFF32>(i + 1, -cx, -cy, -cz), fsx[i + 1], pp.fref[i]);
+        if constexpr (XCH) {
+          const int j = xpair<H>(i), xm = cx > 0 ? xl : xr, xp = cx > 0 ? xr : xl;
+          Store<FS>::st(xf + 2 * j * geo.nx + xp, fsx[i], pp.fref[i]);
+          Store<FS>::st(xf + (2 * j + 1) * geo.nx + xm, fsx[i + 1], pp.fref[i]);
+        } else {
+          Store<FS>::st(pf.template at<OFF32>(i, cx, cy, cz), fsx[i], pp.fref[i]);
+          Store<FS>::st(pf.template at<OFF32>(i + 1, -cx, -cy, -cz), fsx[i + 1], pp.fref[i]);
+        }
       }
     }
     if (uout) {
@@ -1046,10 +1070,20 @@ __device__ __forceinline__ void collide_cell(const Planes<FS, GS>& pl, const T* 
       gi[k] = (T)ld_nt(PAR == 0 ? pg.template at<OFF32>(k, 0, 0, 0)
                                 : pg.template at<OFF32>(opp(k), 0, -P::cy[k], -P::cz[k]));
     }
+    if constexpr (XCH) {
 #pragma unroll
-    for (int k = 0; k < QG; ++k) {
-      if (PAR == 0 || P::cx[k] == 0) continue;
-      gi[k] = (T)*pg.template at<OFF32>(opp(k), -P::cx[k], -P::cy[k], -P::cz[k]);
+      for (int k = 1; k < QG; k += 2) {
+        if (P::cx[k] == 0) continue;
+        const int j = xpair<P>(k), xm = P::cx[k] > 0 ? xl : xr, xp = P::cx[k] > 0 ? xr : xl;
+        gi[k] = (T)xg[(2 * j + 1) * geo.nx + xm];
+        gi[k + 1] = (T)xg[2 * j * geo.nx + xp];
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < QG; ++k) {
+        if (PAR == 0 || P::cx[k] == 0) continue;
+        gi[k] = (T)*pg.template at<OFF32>(opp(k), -P::cx[k], -P::cy[k], -P::cz[k]);
+      }
     }
     // geq - g is formed with the product unrounded: a rounded w_k (phi + c.j/cs^2)
     // (the D2Q9 weights are not powers of two) would bias the phase-field mass
@@ -1079,8 +1113,14 @@ __device__ __forceinline__ void collide_cell(const Planes<FS, GS>& pl, const T* 
       for (int k = 1; k < QG; k += 2) {
         const int cx = P::cx[k], cy = P::cy[k], cz = P::cz[k];
         if (cx == 0) continue;
-        *pg.template at<OFF32>(k, cx, cy, cz) = gsx[k];
-        *pg.template at<OFF32>(k + 1, -cx, -cy, -cz) = gsx[k + 1];
+        if constexpr (XCH) {
+          const int j = xpair<P>(k), xm = cx > 0 ? xl : xr, xp = cx > 0 ? xr : xl;
+          xg[2 * j * geo.nx + xp] = gsx[k];
+          xg[(2 * j + 1) * geo.nx + xm] = gsx[k + 1];
+        } else {
+          *pg.template at<OFF32>(k, cx, cy, cz) = gsx[k];
+          *pg.template at<OFF32>(k + 1, -cx, -cy, -cz) = gsx[k + 1];
+        }
       }
     }
     }
@@ -1146,6 +1186,117 @@ __global__ __launch_bounds__(NT) void k_collide(Planes<FS, GS> pl, const T* __re
     collide_cell<DIM, QH, PAR, MODE, T, FS, GS, OFF32>(pl, phi, J, flags, geo, pp, nci_on, macro, uout, x, y, z,
                                                        acc);
   if constexpr (MODE != MODE_STEP) block_partials(acc, partials);
+}
+
+// Raw bits of a stored population (what the staging copies move).
+template <typename E>
+struct Bits {
+  using type = E;
+};
+template <>
+struct Bits<__half> {
+  using type = unsigned short;
+};
+template <>
+struct Bits<__hip_bfloat16> {
+  using type = unsigned short;
+};
+
+// LDS bytes of k_collide_row for rows of nx cells: the x-shifted hydrodynamic
+// pairs, then (at a 16-byte boundary) the x-shifted phase-field pairs.
+template <int DIM, int QH, typename FS, typename GS>
+__host__ __device__ constexpr unsigned xrow_f_bytes(int nx) {
+  return (unsigned)((2 * xpair<HydroQ<QH>>(QH) * nx * (int)sizeof(FS) + 15) & ~15);
+}
+template <int DIM, int QH, typename FS, typename GS>
+__host__ __device__ constexpr unsigned xrow_bytes(int nx) {
+  return xrow_f_bytes<DIM, QH, FS, GS>(nx) + (unsigned)(2 * xpair<Phase<DIM>>(Phase<DIM>::Q) * nx * (int)sizeof(GS));
+}
+
+// Fused collide + stream of the odd AA parity (3D), one block per x row.  In
+// the odd parity a cell reads and writes its neighbours' slots, so the accesses
+// of directions with c_x != 0 sit one cell off the row's alignment and the
+// lines at block edges are shared by two blocks.  Here the block owns whole
+// rows of those slots: it reads them aligned and streaming into LDS, the cells
+// exchange their values there, and the rows go back aligned.  Each staged
+// element is read and then written by exactly one cell (AA streaming swaps
+// values in place), so the cells need no barrier among themselves; a row
+// (y', z') of slot i is staged only by the block of row (y' - c_y, z' - c_z).
+// Rows map to XCDs as the planes of slab_block: XCD k takes the planes k,
+// k + 8, ... .
+template <int QH, typename T, typename FS, typename GS, bool OFF32>
+__global__ __launch_bounds__(NT) void k_collide_row(Planes<FS, GS> pl, const T* __restrict__ phi,
+                                                    const T* __restrict__ J,
+                                                    const unsigned* __restrict__ flags,
+                                                    unsigned* __restrict__ cnt_other, Geo geo,
+                                                    PhysT<T> pp, int nci_on, T* __restrict__ uout) {
+  using H = HydroQ<QH>;
+  using P = Phase<3>;
+  using BF = typename Bits<FS>::type;
+  using BG = typename Bits<GS>::type;
+  extern __shared__ __align__(16) unsigned char xlds[];
+  const int nx = geo.nx;
+  FS* xf = (FS*)xlds;
+  GS* xg = (GS*)(xlds + xrow_f_bytes<3, QH, FS, GS>(nx));
+  BF* bf = (BF*)xf;
+  BG* bg = (BG*)xg;
+  if (nci_on && blockIdx.x == 0 && threadIdx.x == 0) *cnt_other = 0u;
+  int r = blockIdx.x;
+  {
+    const int per = geo.ny, full = (geo.nz & ~7) * per;
+    if (r < full) {
+      const int k = r & 7, i = r >> 3;
+      r = (k + 8 * (i / per)) * per + i % per;
+    }
+  }
+  const int y = r % geo.ny, z = r / geo.ny;
+  const bool phase = uout == nullptr;   // LBM phase field (the FD one has no g)
+  for (int p = (int)threadIdx.x; p < nx; p += NT) {
+    const PopNbr<const FS> pf(pl.f, p, y, z, geo, H::Q);
+#pragma unroll
+    for (int i = 1; i < H::Q; i += 2) {
+      if (H::cx[i] == 0) continue;
+      const int j = xpair<H>(i);
+      bf[2 * j * nx + p] = ld_nt((const BF*)pf.template at<OFF32>(i, 0, H::cy[i], H::cz[i]));
+      bf[(2 * j + 1) * nx + p] = ld_nt((const BF*)pf.template at<OFF32>(i + 1, 0, -H::cy[i], -H::cz[i]));
+    }
+    if (phase) {
+      const PopNbr<const GS> pg(pl.g, p, y, z, geo, P::Q);
+#pragma unroll
+      for (int k = 1; k < P::Q; k += 2) {
+        if (P::cx[k] == 0) continue;
+        const int j = xpair<P>(k);
+        bg[2 * j * nx + p] = ld_nt((const BG*)pg.template at<OFF32>(k, 0, P::cy[k], P::cz[k]));
+        bg[(2 * j + 1) * nx + p] = ld_nt((const BG*)pg.template at<OFF32>(k + 1, 0, -P::cy[k], -P::cz[k]));
+      }
+    }
+  }
+  __syncthreads();
+  double acc[NPART];   // not used by the plain step
+  for (int x = (int)threadIdx.x; x < nx; x += NT)
+    collide_cell<3, QH, 1, MODE_STEP, T, FS, GS, OFF32, true>(pl, phi, J, flags, geo, pp, nci_on, nullptr,
+                                                             uout, x, y, z, acc, xf, xg);
+  __syncthreads();
+  for (int p = (int)threadIdx.x; p < nx; p += NT) {
+    const PopNbr<FS> pf(pl.f, p, y, z, geo, H::Q);
+#pragma unroll
+    for (int i = 1; i < H::Q; i += 2) {
+      if (H::cx[i] == 0) continue;
+      const int j = xpair<H>(i);
+      st_nt((BF*)pf.template at<OFF32>(i, 0, H::cy[i], H::cz[i]), bf[2 * j * nx + p]);
+      st_nt((BF*)pf.template at<OFF32>(i + 1, 0, -H::cy[i], -H::cz[i]), bf[(2 * j + 1) * nx + p]);
+    }
+    if (phase) {
+      const PopNbr<GS> pg(pl.g, p, y, z, geo, P::Q);
+#pragma unroll
+      for (int k = 1; k < P::Q; k += 2) {
+        if (P::cx[k] == 0) continue;
+        const int j = xpair<P>(k);
+        st_nt((BG*)pg.template at<OFF32>(k, 0, P::cy[k], P::cz[k]), bg[2 * j * nx + p]);
+        st_nt((BG*)pg.template at<OFF32>(k + 1, 0, -P::cy[k], -P::cz[k]), bg[(2 * j + 1) * nx + p]);
+      }
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------

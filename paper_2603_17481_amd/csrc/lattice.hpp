@@ -120,4 +120,13 @@ __host__ __device__ constexpr T wt(int i) {
 
 __host__ __device__ constexpr int opp(int i) { return i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1); }
 
+// Rank of the odd direction i among the odd directions of lattice L with
+// c_x != 0 (the pairs whose streaming shifts along x); xpair<L>(L::Q) counts them.
+template <typename L>
+__host__ __device__ constexpr int xpair(int i) {
+  int r = 0;
+  for (int j = 1; j < i; j += 2) r += L::cx[j] != 0 ? 1 : 0;
+  return r;
+}
+
 }  // namespace lbm

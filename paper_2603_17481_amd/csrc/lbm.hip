@@ -397,9 +397,28 @@ struct Engine {
     return widest < (size_t(1) << 32);
   }
 
+  // The odd parity's plain step runs one block per x row (k_collide_row) when
+  // the staged rows fit in 64 KB of LDS and a row fills a block.
+  static bool row_collide(const lbm_ctx* c) {
+    if constexpr (DIM != 3) return false;
+    const int nx = c->p.nx;
+    return nx >= NT && nx % 64 == 0 && xrow_bytes<DIM, QH, FS, GS>(nx) <= 64u * 1024u;
+  }
+
   template <int MODE>
   static void collide_pass(lbm_ctx* c, int par, T* macro) {
     const bool o32 = off32(c);
+    if constexpr (DIM == 3 && MODE == MODE_STEP) {
+      if (par == 1 && row_collide(c)) {
+        auto k = o32 ? k_collide_row<QH, T, FS, GS, true> : k_collide_row<QH, T, FS, GS, false>;
+        const unsigned lds = xrow_bytes<DIM, QH, FS, GS>(c->p.nx);
+        Timed tm(c, 2);
+        hipLaunchKernelGGL(k, dim3((unsigned)(c->p.ny * c->p.nz)), dim3(NT), lds, c->stream, planes(c), (const T*)c->phi(),
+                           (const T*)c->J(), (const unsigned*)c->flags(par), c->cnt() + (1 - par), c->geo,
+                           physT(c), c->nci_on() ? 1 : 0, c->fd() ? (T*)c->ua() : (T*)nullptr);
+        return;
+      }
+    }
     auto k = par == 0
                  ? (o32 ? k_collide<DIM, QH, 0, MODE, T, FS, GS, true> : k_collide<DIM, QH, 0, MODE, T, FS, GS, false>)
                  : (o32 ? k_collide<DIM, QH, 1, MODE, T, FS, GS, true> : k_collide<DIM, QH, 1, MODE, T, FS, GS, false>);
