@@ -499,19 +499,26 @@ __device__ __forceinline__ void nci_tile(NciShared<DIM, T>& sm, unsigned t, cons
   const int tz = (int)(t / ((unsigned)geo.ntx * (unsigned)geo.nty));
   const int ox = tx * TX, oy = ty * TY, oz = tz * TZ;
   if (threadIdx.x == 0) sm.ng = 0;
-  // (1) phi tile with halo: lanes along x (one row of PX cells per PX lanes)
+  // (1) phi tile with halo: lanes along x (one row of PX cells per PX lanes).
+  // The passes have a compile-time count, so that all of a lane's loads are
+  // issued before the first one is waited for.
   {
     constexpr int RPI = NT_NCI / PX;                 // rows per pass
     constexpr int NROW = NPH / PX;
+    constexpr int NPASS = (NROW + RPI - 1) / RPI;
     const int ex = (int)threadIdx.x % PX, rr = (int)threadIdx.x / PX;
     const int gx = wrap_near(ox + ex - PHI_HALO, geo.nx);
-    if (rr < RPI)
-      for (int r = rr; r < NROW; r += RPI) {
+    if (rr < RPI) {
+#pragma unroll
+      for (int it = 0; it < NPASS; ++it) {
+        const int r = rr + it * RPI;
+        if (NROW % RPI != 0 && r >= NROW) break;
         const int ey = r % PY, ez = r / PY;
         const int gy = wrap_near(oy + ey - PHI_HALO, geo.ny);
         const int gz = DIM == 3 ? wrap_near(oz + ez - PHI_HALO, geo.nz) : 0;
         sm.phs[ex + PX * r] = phi[gx + geo.nx * (gy + geo.ny * gz)];
       }
+    }
   }
   __syncthreads();
   // (2) indicator everywhere on tile + 3, normal where the indicator passes the gate
@@ -555,8 +562,12 @@ __device__ __forceinline__ void nci_tile(NciShared<DIM, T>& sm, unsigned t, cons
       const int bx = (wv & 1) * SX, by = ((wv >> 1) & 1) * SY, bz = DIM == 3 ? (wv >> 2) * SZ : 0;
       const int rx = lane % RX, rr = lane / RX;
       T lo[3] = {(T)1, (T)1, (T)1}, hi[3] = {(T)-1, (T)-1, (T)-1};
+      constexpr int NPASS = (RY * RZ + RPI - 1) / RPI;
       if (rr < RPI)
-        for (int r = rr; r < RY * RZ; r += RPI) {
+#pragma unroll 6
+        for (int it = 0; it < NPASS; ++it) {
+          const int r = rr + it * RPI;
+          if ((RY * RZ) % RPI != 0 && r >= RY * RZ) break;
           const int ry = r % RY, rz = r / RY;
           const NQ<T> v = sm.nq[(bx + rx) + NX * ((by + ry) + NY * (bz + rz))];
           if (v.q >= q_th) {
@@ -782,7 +793,7 @@ __device__ __forceinline__ void nci_tile_w(NciShared<DIM, T>& sm, unsigned t, co
 }
 
 template <int DIM, int QH, typename T, bool DEBUG>
-__global__ __launch_bounds__(NT_NCI) void k_nci(const T* __restrict__ phi, T* __restrict__ J,
+__global__ __launch_bounds__(NT_NCI) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 1))) void k_nci(const T* __restrict__ phi, T* __restrict__ J,
                                                 int* __restrict__ chi_out, int* __restrict__ part_out,
                                                 const unsigned* __restrict__ list,
                                                 const unsigned* __restrict__ cnt,
@@ -1874,7 +1885,7 @@ __global__ __launch_bounds__(NT) void k_phi_multi(const Job<T, FS, GS>* __restri
 }
 
 template <int DIM, int QH, typename T, typename FS, typename GS>
-__global__ __launch_bounds__(NT_NCI) void k_nci_multi(const Job<T, FS, GS>* __restrict__ jobs,
+__global__ __launch_bounds__(NT_NCI) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 1))) void k_nci_multi(const Job<T, FS, GS>* __restrict__ jobs,
                                                       int njobs, int s) {
   __shared__ NciShared<DIM, T> sm;
   for (int j = 0; j < njobs; ++j) {
