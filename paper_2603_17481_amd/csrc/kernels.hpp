@@ -1215,13 +1215,13 @@ struct Bits<__hip_bfloat16> {
 
 // LDS bytes of k_collide_row for rows of nx cells: the x-shifted hydrodynamic
 // pairs, then (at a 16-byte boundary) the x-shifted phase-field pairs.
-template <int DIM, int QH, typename FS, typename GS>
+template <int QH, typename FS>
 __host__ __device__ constexpr unsigned xrow_f_bytes(int nx) {
   return (unsigned)((2 * xpair<HydroQ<QH>>(QH) * nx * (int)sizeof(FS) + 15) & ~15);
 }
 template <int DIM, int QH, typename FS, typename GS>
 __host__ __device__ constexpr unsigned xrow_bytes(int nx) {
-  return xrow_f_bytes<DIM, QH, FS, GS>(nx) + (unsigned)(2 * xpair<Phase<DIM>>(Phase<DIM>::Q) * nx * (int)sizeof(GS));
+  return xrow_f_bytes<QH, FS>(nx) + (unsigned)(2 * xpair<Phase<DIM>>(Phase<DIM>::Q) * nx * (int)sizeof(GS));
 }
 
 // Fused collide + stream of the odd AA parity (3D), one block per x row.  In
@@ -1234,9 +1234,9 @@ __host__ __device__ constexpr unsigned xrow_bytes(int nx) {
 // values in place), so the cells need no barrier among themselves; a row
 // (y', z') of slot i is staged only by the block of row (y' - c_y, z' - c_z).
 // Rows map to XCDs as the planes of slab_block: XCD k takes the planes k,
-// k + 8, ... .
-template <int QH, typename T, typename FS, typename GS, bool OFF32>
-__global__ __launch_bounds__(NT) void k_collide_row(Planes<FS, GS> pl, const T* __restrict__ phi,
+// k + 8, ... .  Blocks have NTR threads, each taking the cells x, x + NTR, ...
+template <int QH, typename T, typename FS, typename GS, bool OFF32, int NTR>
+__global__ __launch_bounds__(NTR) void k_collide_row(Planes<FS, GS> pl, const T* __restrict__ phi,
                                                     const T* __restrict__ J,
                                                     const unsigned* __restrict__ flags,
                                                     unsigned* __restrict__ cnt_other, Geo geo,
@@ -1248,7 +1248,7 @@ __global__ __launch_bounds__(NT) void k_collide_row(Planes<FS, GS> pl, const T* 
   extern __shared__ __align__(16) unsigned char xlds[];
   const int nx = geo.nx;
   FS* xf = (FS*)xlds;
-  GS* xg = (GS*)(xlds + xrow_f_bytes<3, QH, FS, GS>(nx));
+  GS* xg = (GS*)(xlds + xrow_f_bytes<QH, FS>(nx));
   BF* bf = (BF*)xf;
   BG* bg = (BG*)xg;
   if (nci_on && blockIdx.x == 0 && threadIdx.x == 0) *cnt_other = 0u;
@@ -1262,7 +1262,7 @@ __global__ __launch_bounds__(NT) void k_collide_row(Planes<FS, GS> pl, const T* 
   }
   const int y = r % geo.ny, z = r / geo.ny;
   const bool phase = uout == nullptr;   // LBM phase field (the FD one has no g)
-  for (int p = (int)threadIdx.x; p < nx; p += NT) {
+  for (int p = (int)threadIdx.x; p < nx; p += NTR) {
     const PopNbr<const FS> pf(pl.f, p, y, z, geo, H::Q);
 #pragma unroll
     for (int i = 1; i < H::Q; i += 2) {
@@ -1284,11 +1284,11 @@ __global__ __launch_bounds__(NT) void k_collide_row(Planes<FS, GS> pl, const T* 
   }
   __syncthreads();
   double acc[NPART];   // not used by the plain step
-  for (int x = (int)threadIdx.x; x < nx; x += NT)
+  for (int x = (int)threadIdx.x; x < nx; x += NTR)
     collide_cell<3, QH, 1, MODE_STEP, T, FS, GS, OFF32, true>(pl, phi, J, flags, geo, pp, nci_on, nullptr,
                                                              uout, x, y, z, acc, xf, xg);
   __syncthreads();
-  for (int p = (int)threadIdx.x; p < nx; p += NT) {
+  for (int p = (int)threadIdx.x; p < nx; p += NTR) {
     const PopNbr<FS> pf(pl.f, p, y, z, geo, H::Q);
 #pragma unroll
     for (int i = 1; i < H::Q; i += 2) {

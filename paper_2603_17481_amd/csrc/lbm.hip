@@ -398,7 +398,10 @@ struct Engine {
   }
 
   // The odd parity's plain step runs one block per x row (k_collide_row) when
-  // the staged rows fit in 64 KB of LDS and a row fills a block.
+  // the staged rows fit in 64 KB of LDS and a row fills a block.  D3Q19 with
+  // 4-byte populations in rows of a multiple of 512 cells uses 512-thread blocks
+  // (at 512^3 FP32 the step ran 0.5 % faster); every other case 256 (with 16-bit
+  // populations and with D3Q27, 512 threads were slower).
   static bool row_collide(const lbm_ctx* c) {
     if constexpr (DIM != 3) return false;
     const int nx = c->p.nx;
@@ -410,10 +413,12 @@ struct Engine {
     const bool o32 = off32(c);
     if constexpr (DIM == 3 && MODE == MODE_STEP) {
       if (par == 1 && row_collide(c)) {
-        auto k = o32 ? k_collide_row<QH, T, FS, GS, true> : k_collide_row<QH, T, FS, GS, false>;
+        const bool wide = QH == 19 && sizeof(FS) == 4 && c->p.nx % 512 == 0;
+        auto k = wide ? (o32 ? k_collide_row<QH, T, FS, GS, true, 512> : k_collide_row<QH, T, FS, GS, false, 512>)
+                      : (o32 ? k_collide_row<QH, T, FS, GS, true, NT> : k_collide_row<QH, T, FS, GS, false, NT>);
         const unsigned lds = xrow_bytes<DIM, QH, FS, GS>(c->p.nx);
         Timed tm(c, 2);
-        hipLaunchKernelGGL(k, dim3((unsigned)(c->p.ny * c->p.nz)), dim3(NT), lds, c->stream, planes(c), (const T*)c->phi(),
+        hipLaunchKernelGGL(k, dim3((unsigned)(c->p.ny * c->p.nz)), dim3(wide ? 512 : NT), lds, c->stream, planes(c), (const T*)c->phi(),
                            (const T*)c->J(), (const unsigned*)c->flags(par), c->cnt() + (1 - par), c->geo,
                            physT(c), c->nci_on() ? 1 : 0, c->fd() ? (T*)c->ua() : (T*)nullptr);
         return;

@@ -1,6 +1,7 @@
 """The odd AA parity's row kernel (k_collide_row: one block per x row, the
 x-shifted populations exchanged through LDS), used in 3D when nx >= 256 and
-nx % 64 == 0.
+nx % 64 == 0: 512-thread blocks for D3Q19 with 4-byte populations in rows of a
+multiple of 512 cells, 256-thread blocks otherwise.
 
 Its arithmetic is the cell collision of every other collide kernel; only the
 data movement differs.  So (1) in FP64 it must match the CPU oracle to the 1e-12
@@ -8,7 +9,7 @@ bar, for both phase-field solvers and both 3D hydrodynamic lattices, on a
 320-wide box (a row spans one full and one partial pass of the 256-thread
 block); (2) in every storage precision, stepping alone (row kernel on the odd
 steps) must leave the state bit for bit equal to batched stepping, whose kernel
-is the per-cell one.
+is the per-cell one, with either block size (nx = 320 and 512).
 """
 import numpy as np
 import pytest
@@ -22,8 +23,8 @@ pytestmark = pytest.mark.gpu
 FP64_BAR = 1e-12
 
 
-def wide_pair(precision="fp64", **kw):
-    st = near_contact_pair(3, precision, nx=320)
+def wide_pair(precision="fp64", nx=320, **kw):
+    st = near_contact_pair(3, precision, nx=nx)
     return type(st)(st.params.replace(**kw), st.phi, st.u, st.spheres, st.kind)
 
 
@@ -48,12 +49,13 @@ def test_fp64_matches_oracle(hq, solver, steps):
     g.close()
 
 
-@pytest.mark.parametrize("precision,hq", [("fp32", 19), ("fp32", 27), ("fp16", 19), ("bf16", 19),
-                                          ("fp64", 19)])
-def test_alone_equals_batch(precision, hq):
-    announce(f"row collide alone vs batch {precision} D3Q{hq}")
-    states = [wide_pair(precision, hydro_q=hq),
-              wide_pair(precision, hydro_q=hq, diag_interval=7)]
+@pytest.mark.parametrize("precision,hq,nx", [("fp32", 19, 320), ("fp32", 27, 320), ("fp16", 19, 320),
+                                             ("bf16", 19, 320), ("fp64", 19, 320), ("fp32", 19, 512),
+                                             ("fp32", 27, 512), ("fp16", 19, 512)])
+def test_alone_equals_batch(precision, hq, nx):
+    announce(f"row collide alone vs batch {precision} D3Q{hq} nx={nx}")
+    states = [wide_pair(precision, nx, hydro_q=hq),
+              wide_pair(precision, nx, hydro_q=hq, diag_interval=7)]
 
     def build():
         lats = []
