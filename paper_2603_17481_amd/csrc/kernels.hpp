@@ -446,8 +446,15 @@ struct NciShared {
     T gJ[TC][DIM];   // result per gated cell
     int gpart[TC];   // packed partner offset + 1 (0: no partner)
   };
+  // normal ranges of step 2b: per x row and x half (A), then per z plane and
+  // x, y half (B); 6 values each (lo[3], hi[3])
+  struct Ranges {
+    T A[NY * NZ * 2][6];
+    T B[NZ * 4][6];
+  };
   union {
     T phs[NPH];      // phi tile with halo (steps 1-2)
+    Ranges rg;       // step 2b
     Out out;         // results (steps 4-6)
   };
   NQ<T> nq[NNQ];
@@ -550,46 +557,56 @@ __device__ __forceinline__ void nci_tile(NciShared<DIM, T>& sm, unsigned t, cons
   __syncthreads();
   // (2b) per sub-tile (the tile halved along each axis) the range [lo, hi] of
   // each normal component over the gated cells of the region that the windows
-  // of its cells cover.  One wave per sub-tile, lanes along x.
+  // of its cells cover.  Minima and maxima are separable: each thread reduces
+  // a run along x (one x row, one x half), then along y, then along z, with
+  // a barrier between the passes and no cross-lane reductions.
   constexpr int SX = TX / 2, SY = TY / 2, SZ = DIM == 3 ? TZ / 2 : 1;
   {
     constexpr int RX = SX + 2 * NQ_HALO, RY = SY + 2 * NQ_HALO, RZ = DIM == 3 ? SZ + 2 * NQ_HALO : 1;
     constexpr int NSUB = DIM == 3 ? 8 : 4;
-    constexpr int RPI = 64 / RX;
-    static_assert(NSUB <= NT_NCI / 64, "one wave per sub-tile");
-    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    if (wv < NSUB) {
-      const int bx = (wv & 1) * SX, by = ((wv >> 1) & 1) * SY, bz = DIM == 3 ? (wv >> 2) * SZ : 0;
-      const int rx = lane % RX, rr = lane / RX;
-      T lo[3] = {(T)1, (T)1, (T)1}, hi[3] = {(T)-1, (T)-1, (T)-1};
-      constexpr int NPASS = (RY * RZ + RPI - 1) / RPI;
-      if (rr < RPI)
-#pragma unroll 6
-        for (int it = 0; it < NPASS; ++it) {
-          const int r = rr + it * RPI;
-          if ((RY * RZ) % RPI != 0 && r >= RY * RZ) break;
-          const int ry = r % RY, rz = r / RY;
-          const NQ<T> v = sm.nq[(bx + rx) + NX * ((by + ry) + NY * (bz + rz))];
-          if (v.q >= q_th) {
-            const T n[3] = {v.n0, v.n1, v.n2};
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-              lo[a] = n[a] < lo[a] ? n[a] : lo[a];
-              hi[a] = n[a] > hi[a] ? n[a] : hi[a];
-            }
-          }
-        }
+    constexpr int NZ = NciShared<DIM, T>::NZ;
+    static_assert(NY * NZ * 2 <= NT_NCI, "one x run per thread");
+    auto merge = [](T r[6], const T* v) {
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
-        lo[a] = wave_min(lo[a]);
-        hi[a] = wave_max(hi[a]);
+        r[a] = v[a] < r[a] ? v[a] : r[a];
+        r[3 + a] = v[3 + a] > r[3 + a] ? v[3 + a] : r[3 + a];
       }
-      if (lane == 0) {
+    };
+    const int t = threadIdx.x;
+    if (t < NY * NZ * 2) {   // t = 2 (row) + x half
+      const int row = t >> 1, bx = (t & 1) * SX;
+      T r[6] = {(T)1, (T)1, (T)1, (T)-1, (T)-1, (T)-1};
 #pragma unroll
-        for (int a = 0; a < 3; ++a) {
-          sm.box[wv][0][a] = lo[a];
-          sm.box[wv][1][a] = hi[a];
+      for (int i = 0; i < RX; ++i) {
+        const NQ<T> v = sm.nq[bx + i + NX * row];
+        if (v.q >= q_th) {
+          const T n[6] = {v.n0, v.n1, v.n2, v.n0, v.n1, v.n2};
+          merge(r, n);
         }
+      }
+#pragma unroll
+      for (int a = 0; a < 6; ++a) sm.rg.A[t][a] = r[a];
+    }
+    __syncthreads();
+    if (t < NZ * 4) {   // t = 4 z + 2 (y half) + x half
+      const int ez = t >> 2, by = ((t >> 1) & 1) * SY, sx = t & 1;
+      T r[6] = {(T)1, (T)1, (T)1, (T)-1, (T)-1, (T)-1};
+#pragma unroll
+      for (int j = 0; j < RY; ++j) merge(r, sm.rg.A[2 * (by + j + NY * ez) + sx]);
+#pragma unroll
+      for (int a = 0; a < 6; ++a) sm.rg.B[t][a] = r[a];
+    }
+    __syncthreads();
+    if (t < NSUB) {   // t = 4 (z half) + 2 (y half) + x half
+      const int bz = (t >> 2) * SZ;
+      T r[6] = {(T)1, (T)1, (T)1, (T)-1, (T)-1, (T)-1};
+#pragma unroll
+      for (int k = 0; k < RZ; ++k) merge(r, sm.rg.B[4 * (bz + k) + (t & 3)]);
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        sm.box[t][0][a] = r[a];
+        sm.box[t][1][a] = r[3 + a];
       }
     }
     __syncthreads();
