@@ -474,6 +474,47 @@ __device__ __forceinline__ void nci_clear_other(unsigned* __restrict__ flags_oth
     flags_other[list_other[k]] = 0u;
 }
 
+// The phi values of step 1 for one tile, held in registers: lanes along x, one
+// row of PX cells per PX lanes, a compile-time number of passes.  load() is
+// issued for the next tile while the current one is processed, so that its
+// latency is hidden; store() puts the values into the LDS tile.
+template <int DIM, typename T>
+struct NciHalo {
+  using S = NciShared<DIM, T>;
+  using TL = NciTile<DIM, T>;
+  static constexpr int RPI = NT_NCI / S::PX;      // rows per pass
+  static constexpr int NROW = S::NPH / S::PX;
+  static constexpr int NPASS = (NROW + RPI - 1) / RPI;
+  T v[NPASS];
+  __device__ __forceinline__ void load(unsigned t, const T* __restrict__ phi, const Geo& geo) {
+    const int tx = (int)(t % (unsigned)geo.ntx);
+    const int ty = (int)((t / (unsigned)geo.ntx) % (unsigned)geo.nty);
+    const int tz = (int)(t / ((unsigned)geo.ntx * (unsigned)geo.nty));
+    const int ex = (int)threadIdx.x % S::PX, rr = (int)threadIdx.x / S::PX;
+    const int gx = wrap_near(tx * TL::TX + ex - PHI_HALO, geo.nx);
+    if (rr >= RPI) return;
+#pragma unroll
+    for (int it = 0; it < NPASS; ++it) {
+      const int r = rr + it * RPI;
+      if (NROW % RPI != 0 && r >= NROW) break;
+      const int ey = r % S::PY, ez = r / S::PY;
+      const int gy = wrap_near(ty * TL::TY + ey - PHI_HALO, geo.ny);
+      const int gz = DIM == 3 ? wrap_near(tz * TL::TZ + ez - PHI_HALO, geo.nz) : 0;
+      v[it] = phi[gx + geo.nx * (gy + geo.ny * gz)];
+    }
+  }
+  __device__ __forceinline__ void store(S& sm) const {
+    const int ex = (int)threadIdx.x % S::PX, rr = (int)threadIdx.x / S::PX;
+    if (rr >= RPI) return;
+#pragma unroll
+    for (int it = 0; it < NPASS; ++it) {
+      const int r = rr + it * RPI;
+      if (NROW % RPI != 0 && r >= NROW) break;
+      sm.phs[ex + S::PX * r] = v[it];
+    }
+  }
+};
+
 // Per listed tile: (1) phi with a halo of 4 into LDS; (2) q on tile + 3 and
 // n where q >= q_th, packed with q; (3) the gated cells of the tile are listed;
 // (4) each gated cell gets an 8-lane group whose lanes scan one window plane
@@ -485,7 +526,8 @@ __device__ __forceinline__ void nci_clear_other(unsigned* __restrict__ flags_oth
 // (5) the group leader builds J (Sec. 2.3.3) and the tile's J is written from
 // LDS, zero for cells without a partner.
 template <int DIM, int QH, typename T, bool DEBUG, int WR>
-__device__ __forceinline__ void nci_tile(NciShared<DIM, T>& sm, unsigned t, const T* __restrict__ phi,
+__device__ __forceinline__ void nci_tile(NciShared<DIM, T>& sm, unsigned t, NciHalo<DIM, T>& halo, bool next,
+                                         unsigned tn, const T* __restrict__ phi,
                                          T* __restrict__ J, int* __restrict__ chi_out,
                                          int* __restrict__ part_out, const Geo& geo, const NciP& np,
                                          unsigned& my_active) {
@@ -495,7 +537,7 @@ __device__ __forceinline__ void nci_tile(NciShared<DIM, T>& sm, unsigned t, cons
   constexpr int TC = TX * TY * TZ;
   constexpr int PX = NciShared<DIM, T>::PX, PY = NciShared<DIM, T>::PY;
   constexpr int NX = NciShared<DIM, T>::NX, NY = NciShared<DIM, T>::NY;
-  constexpr int NPH = NciShared<DIM, T>::NPH, NNQ = NciShared<DIM, T>::NNQ;
+  constexpr int NNQ = NciShared<DIM, T>::NNQ;
   static_assert(WR >= 1 && WR <= NQ_HALO, "window radius");
   const T q_th = (T)np.q_th, eta = (T)np.eta, cos_opp = (T)np.cos_opp, eps_n = (T)np.eps_n,
           eps_q = (T)np.eps_q, tie = (T)np.tie_eps;
@@ -506,28 +548,12 @@ __device__ __forceinline__ void nci_tile(NciShared<DIM, T>& sm, unsigned t, cons
   const int tz = (int)(t / ((unsigned)geo.ntx * (unsigned)geo.nty));
   const int ox = tx * TX, oy = ty * TY, oz = tz * TZ;
   if (threadIdx.x == 0) sm.ng = 0;
-  // (1) phi tile with halo: lanes along x (one row of PX cells per PX lanes).
-  // The passes have a compile-time count, so that all of a lane's loads are
-  // issued before the first one is waited for.
-  {
-    constexpr int RPI = NT_NCI / PX;                 // rows per pass
-    constexpr int NROW = NPH / PX;
-    constexpr int NPASS = (NROW + RPI - 1) / RPI;
-    const int ex = (int)threadIdx.x % PX, rr = (int)threadIdx.x / PX;
-    const int gx = wrap_near(ox + ex - PHI_HALO, geo.nx);
-    if (rr < RPI) {
-#pragma unroll
-      for (int it = 0; it < NPASS; ++it) {
-        const int r = rr + it * RPI;
-        if (NROW % RPI != 0 && r >= NROW) break;
-        const int ey = r % PY, ez = r / PY;
-        const int gy = wrap_near(oy + ey - PHI_HALO, geo.ny);
-        const int gz = DIM == 3 ? wrap_near(oz + ez - PHI_HALO, geo.nz) : 0;
-        sm.phs[ex + PX * r] = phi[gx + geo.nx * (gy + geo.ny * gz)];
-      }
-    }
-  }
+  // (1) phi tile with halo (loaded into registers before: for the first tile by
+  // the caller, for the others during the previous tile), then the next
+  // tile's loads are issued
+  halo.store(sm);
   __syncthreads();
+  if (next) halo.load(tn, phi, geo);
   // (2) indicator everywhere on tile + 3, normal where the indicator passes the gate
   {
     constexpr int RPI = NT_NCI / NX;
@@ -800,13 +826,35 @@ __device__ __forceinline__ void nci_tile(NciShared<DIM, T>& sm, unsigned t, cons
 
 // The tile routine with the window radius as a compile-time constant.
 template <int DIM, int QH, typename T, bool DEBUG>
-__device__ __forceinline__ void nci_tile_w(NciShared<DIM, T>& sm, unsigned t, const T* __restrict__ phi,
+__device__ __forceinline__ void nci_tile_w(NciShared<DIM, T>& sm, unsigned t, NciHalo<DIM, T>& halo,
+                                           bool next, unsigned tn, const T* __restrict__ phi,
                                            T* __restrict__ J, int* __restrict__ chi_out,
                                            int* __restrict__ part_out, const Geo& geo, const NciP& np,
                                            unsigned& my_active) {
-  if (np.w == 3) nci_tile<DIM, QH, T, DEBUG, 3>(sm, t, phi, J, chi_out, part_out, geo, np, my_active);
-  else if (np.w == 2) nci_tile<DIM, QH, T, DEBUG, 2>(sm, t, phi, J, chi_out, part_out, geo, np, my_active);
-  else nci_tile<DIM, QH, T, DEBUG, 1>(sm, t, phi, J, chi_out, part_out, geo, np, my_active);
+  if (np.w == 3)
+    nci_tile<DIM, QH, T, DEBUG, 3>(sm, t, halo, next, tn, phi, J, chi_out, part_out, geo, np, my_active);
+  else if (np.w == 2)
+    nci_tile<DIM, QH, T, DEBUG, 2>(sm, t, halo, next, tn, phi, J, chi_out, part_out, geo, np, my_active);
+  else
+    nci_tile<DIM, QH, T, DEBUG, 1>(sm, t, halo, next, tn, phi, J, chi_out, part_out, geo, np, my_active);
+}
+
+// The tiles list[first], list[first + stride], ... of one lattice, each
+// tile's phi loads issued during the previous tile.
+template <int DIM, int QH, typename T, bool DEBUG>
+__device__ __forceinline__ void nci_tiles(NciShared<DIM, T>& sm, const unsigned* __restrict__ list,
+                                          unsigned ntiles, unsigned first, unsigned stride,
+                                          const T* __restrict__ phi, T* __restrict__ J,
+                                          int* __restrict__ chi_out, int* __restrict__ part_out,
+                                          const Geo& geo, const NciP& np, unsigned& my_active) {
+  NciHalo<DIM, T> halo;
+  if (first < ntiles) halo.load(list[first], phi, geo);
+  for (unsigned k = first; k < ntiles; k += stride) {
+    const unsigned kn = k + stride;
+    const bool next = kn < ntiles;
+    nci_tile_w<DIM, QH, T, DEBUG>(sm, list[k], halo, next, next ? list[kn] : 0u, phi, J, chi_out, part_out,
+                                  geo, np, my_active);
+  }
 }
 
 template <int DIM, int QH, typename T, bool DEBUG>
@@ -822,8 +870,8 @@ __global__ __launch_bounds__(NT_NCI) __attribute__((amdgpu_waves_per_eu(sizeof(T
   nci_clear_other(flags_other, list_other, cnt_other);
   const unsigned ntiles = *cnt;
   unsigned my_active = 0;
-  for (unsigned k = blockIdx.x; k < ntiles; k += gridDim.x)
-    nci_tile_w<DIM, QH, T, DEBUG>(sm, list[k], phi, J, chi_out, part_out, geo, np, my_active);
+  nci_tiles<DIM, QH, T, DEBUG>(sm, list, ntiles, blockIdx.x, gridDim.x, phi, J, chi_out, part_out, geo, np,
+                               my_active);
   my_active = wave_sum(my_active);
   if ((threadIdx.x & 63) == 0 && my_active) atomicAdd(nci_count, my_active);
 }
@@ -1912,8 +1960,8 @@ __global__ __launch_bounds__(NT_NCI) __attribute__((amdgpu_waves_per_eu(sizeof(T
     nci_clear_other(jb.flags[1 - par], jb.list[1 - par], jb.cnt + (1 - par));
     const unsigned ntiles = jb.cnt[par];
     unsigned act = 0;
-    for (unsigned k = blockIdx.x; k < ntiles; k += gridDim.x)
-      nci_tile_w<DIM, QH, T, false>(sm, jb.list[par][k], jb.phi, jb.J, nullptr, nullptr, jb.geo, jb.np, act);
+    nci_tiles<DIM, QH, T, false>(sm, jb.list[par], ntiles, blockIdx.x, gridDim.x, jb.phi, jb.J, nullptr, nullptr,
+                                 jb.geo, jb.np, act);
     act = wave_sum(act);
     if ((threadIdx.x & 63) == 0 && act) atomicAdd(jb.cnt + 2, act);
   }
