@@ -152,3 +152,25 @@ def test_diagnostics_do_not_perturb_the_state(precision):
     assert same_state(a, b)
     a.close()
     b.close()
+
+
+def test_batch_equals_alone_with_more_tiles_than_blocks():
+    """A 192^3 swarm of 180 bubbles lists about 3100 near-contact tiles, more than
+    the 2048 blocks of the near-contact kernels, so blocks take a second tile
+    whose phi halo is loaded while the first is processed (alone and in the
+    batch).  The two must still agree bit for bit."""
+    st = W.config_swarm(n=192, bubbles=180, rmin=5.0, rmax=7.0, gap=2.0, seed=5, precision="fp32")
+    p = st.params
+    ph = np.clip(st.phi, 0.0, 1.0)
+    t = p.nx // 8
+    listed = ((ph * (1.0 - ph)) >= p.q_th).reshape(t, 8, t, 8, t, 8).any(axis=(1, 3, 5)).sum()
+    assert listed > 2048
+    announce(f"batch vs alone, 192^3 swarm with {listed} listed tiles")
+    alone, batch = build([st], [0]), build([st], [0])
+    for n in (9, 4):
+        alone[0].step(n)
+        L.lbm_batch_step(batch, n)
+    assert same_state(alone[0], batch[0])
+    assert alone[0].diagnostics()["nci_active"] > 0
+    for g in alone + batch:
+        g.close()
