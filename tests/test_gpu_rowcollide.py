@@ -9,7 +9,8 @@ bar, for both phase-field solvers and both 3D hydrodynamic lattices, on a
 320-wide box (a row spans one full and one partial pass of the 256-thread
 block); (2) in every storage precision, stepping alone (row kernel on the odd
 steps) must leave the state bit for bit equal to batched stepping, whose kernel
-is the per-cell one, with either block size (nx = 320 and 512).
+is the per-cell one, with either block size and one to four cells per thread
+(nx = 320, 512, 768, 1024).
 """
 import numpy as np
 import pytest
@@ -51,7 +52,8 @@ def test_fp64_matches_oracle(hq, solver, steps):
 
 @pytest.mark.parametrize("precision,hq,nx", [("fp32", 19, 320), ("fp32", 27, 320), ("fp16", 19, 320),
                                              ("bf16", 19, 320), ("fp64", 19, 320), ("fp32", 19, 512),
-                                             ("fp32", 27, 512), ("fp16", 19, 512)])
+                                             ("fp32", 27, 512), ("fp16", 19, 512), ("fp32", 19, 768),
+                                             ("fp32", 19, 1024)])
 def test_alone_equals_batch(precision, hq, nx):
     announce(f"row collide alone vs batch {precision} D3Q{hq} nx={nx}")
     states = [wide_pair(precision, nx, hydro_q=hq),
