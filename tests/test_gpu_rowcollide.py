@@ -9,7 +9,7 @@ bar, for both phase-field solvers and both 3D hydrodynamic lattices, on a
 320-wide box (a row spans one full and one partial pass of the 256-thread
 block); (2) in every storage precision, stepping alone (row kernel on the odd
 steps) must leave the state bit for bit equal to batched stepping, whose kernel
-is the per-cell one, with either block size and one to four cells per thread
+is the per-cell one, with either block size and one to three cells per thread
 (nx = 320, 512, 768, 1024).
 """
 import numpy as np
