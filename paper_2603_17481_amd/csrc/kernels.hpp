@@ -932,14 +932,15 @@ __device__ __forceinline__ double m_rcp(double a) { return 1.0 / a; }
 // contributions to the FP64 diagnostics; MODE_DRY leaves the populations and
 // writes p*, rho, u, F to macro (when given).
 template <int DIM, int QH, int PAR, int MODE, typename T, typename FS, typename GS, bool OFF32,
-          bool XCH = false>
+          bool XCH = false, bool PRE = false>
 __device__ __forceinline__ void collide_cell(const Planes<FS, GS>& pl, const T* __restrict__ phi,
                                              const T* __restrict__ J,
                                              const unsigned* __restrict__ flags, const Geo& geo,
                                              const PhysT<T>& pp, int nci_on, T* __restrict__ macro,
                                              T* __restrict__ uout, int x, int y, int z,
                                              double acc[NPART], FS* xf = nullptr,
-                                             GS* xg = nullptr) {
+                                             GS* xg = nullptr, const T* fpre = nullptr,
+                                             const T* gpre = nullptr) {
   using H = HydroQ<QH>;
   using P = Phase<DIM>;
   using TL = NciTile<DIM, T>;
@@ -950,7 +951,9 @@ __device__ __forceinline__ void collide_cell(const Planes<FS, GS>& pl, const T* 
   // XCH (k_collide_row): the odd parity's x-shifted populations of this cell's
   // row are staged in LDS, xf / xg holding for x-shifted pair j (odd direction
   // i) the row of slot i at (y + c_y, z + c_z) at 2 j nx and the row of slot
-  // i + 1 at (y - c_y, z - c_z) at (2 j + 1) nx.
+  // i + 1 at (y - c_y, z - c_z) at (2 j + 1) nx.  PRE: the populations of the
+  // directions with c_x = 0 were loaded by the caller (fpre, gpre, indexed by
+  // direction), before its staging barrier.
   const int xl = x == 0 ? geo.nx - 1 : x - 1, xr = x == geo.nx - 1 ? 0 : x + 1;
   // Population accesses stream past the caches (nontemporal) where they are
   // aligned: every access of the even parity, and the odd parity's accesses of
@@ -983,9 +986,12 @@ __device__ __forceinline__ void collide_cell(const Planes<FS, GS>& pl, const T* 
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
     if (PAR == 1 && H::cx[i] != 0) continue;
-    fi[i] = Store<FS>::ldh(PAR == 0 ? pf.template at<OFF32>(i, 0, 0, 0)
-                                    : pf.template at<OFF32>(opp(i), 0, -H::cy[i], -H::cz[i]),
-                           pp.fref[i]);
+    if constexpr (PRE)
+      fi[i] = fpre[i];
+    else
+      fi[i] = Store<FS>::ldh(PAR == 0 ? pf.template at<OFF32>(i, 0, 0, 0)
+                                      : pf.template at<OFF32>(opp(i), 0, -H::cy[i], -H::cz[i]),
+                             pp.fref[i]);
   }
   if constexpr (XCH) {
 #pragma unroll
@@ -1143,8 +1149,11 @@ __device__ __forceinline__ void collide_cell(const Planes<FS, GS>& pl, const T* 
 #pragma unroll
     for (int k = 0; k < QG; ++k) {
       if (PAR == 1 && P::cx[k] != 0) continue;
-      gi[k] = (T)ld_nt(PAR == 0 ? pg.template at<OFF32>(k, 0, 0, 0)
-                                : pg.template at<OFF32>(opp(k), 0, -P::cy[k], -P::cz[k]));
+      if constexpr (PRE)
+        gi[k] = gpre[k];
+      else
+        gi[k] = (T)ld_nt(PAR == 0 ? pg.template at<OFF32>(k, 0, 0, 0)
+                                  : pg.template at<OFF32>(opp(k), 0, -P::cy[k], -P::cz[k]));
     }
     if constexpr (XCH) {
 #pragma unroll
@@ -1300,7 +1309,10 @@ __host__ __device__ constexpr unsigned xrow_bytes(int nx) {
 // (y', z') of slot i is staged only by the block of row (y' - c_y, z' - c_z).
 // Rows map to XCDs as the planes of slab_block: XCD k takes the planes k,
 // k + 8, ... .  Blocks have NTR threads, each taking the cells x, x + NTR, ...
-template <int QH, typename T, typename FS, typename GS, bool OFF32, int NTR>
+// With ONE (nx = NTR, one cell per thread) each thread also issues its cell's
+// loads of the directions with c_x = 0 before the staging barrier, so that all
+// of the cell's population loads are in flight together.
+template <int QH, typename T, typename FS, typename GS, bool OFF32, int NTR, bool ONE = false>
 __global__ __launch_bounds__(NTR) void k_collide_row(Planes<FS, GS> pl, const T* __restrict__ phi,
                                                     const T* __restrict__ J,
                                                     const unsigned* __restrict__ flags,
@@ -1327,6 +1339,23 @@ __global__ __launch_bounds__(NTR) void k_collide_row(Planes<FS, GS> pl, const T*
   }
   const int y = r % geo.ny, z = r / geo.ny;
   const bool phase = uout == nullptr;   // LBM phase field (the FD one has no g)
+  T fpre[H::Q], gpre[P::Q];
+  if constexpr (ONE) {
+    const PopNbr<const FS> pc(pl.f, (int)threadIdx.x, y, z, geo, H::Q);
+#pragma unroll
+    for (int i = 0; i < H::Q; ++i) {
+      if (H::cx[i] != 0) continue;
+      fpre[i] = Store<FS>::ldh(pc.template at<OFF32>(opp(i), 0, -H::cy[i], -H::cz[i]), pp.fref[i]);
+    }
+    if (phase) {
+      const PopNbr<const GS> pgc(pl.g, (int)threadIdx.x, y, z, geo, P::Q);
+#pragma unroll
+      for (int k = 0; k < P::Q; ++k) {
+        if (P::cx[k] != 0) continue;
+        gpre[k] = (T)ld_nt(pgc.template at<OFF32>(opp(k), 0, -P::cy[k], -P::cz[k]));
+      }
+    }
+  }
   for (int p = (int)threadIdx.x; p < nx; p += NTR) {
     const PopNbr<const FS> pf(pl.f, p, y, z, geo, H::Q);
 #pragma unroll
@@ -1349,9 +1378,14 @@ __global__ __launch_bounds__(NTR) void k_collide_row(Planes<FS, GS> pl, const T*
   }
   __syncthreads();
   double acc[NPART];   // not used by the plain step
-  for (int x = (int)threadIdx.x; x < nx; x += NTR)
-    collide_cell<3, QH, 1, MODE_STEP, T, FS, GS, OFF32, true>(pl, phi, J, flags, geo, pp, nci_on, nullptr,
-                                                             uout, x, y, z, acc, xf, xg);
+  if constexpr (ONE) {
+    collide_cell<3, QH, 1, MODE_STEP, T, FS, GS, OFF32, true, true>(
+        pl, phi, J, flags, geo, pp, nci_on, nullptr, uout, (int)threadIdx.x, y, z, acc, xf, xg, fpre, gpre);
+  } else {
+    for (int x = (int)threadIdx.x; x < nx; x += NTR)
+      collide_cell<3, QH, 1, MODE_STEP, T, FS, GS, OFF32, true>(pl, phi, J, flags, geo, pp, nci_on, nullptr,
+                                                               uout, x, y, z, acc, xf, xg);
+  }
   __syncthreads();
   for (int p = (int)threadIdx.x; p < nx; p += NTR) {
     const PopNbr<FS> pf(pl.f, p, y, z, geo, H::Q);

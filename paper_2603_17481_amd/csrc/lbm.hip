@@ -414,8 +414,11 @@ struct Engine {
     if constexpr (DIM == 3 && MODE == MODE_STEP) {
       if (par == 1 && row_collide(c)) {
         const bool wide = QH == 19 && sizeof(FS) == 4 && c->p.nx % 512 == 0;
-        auto k = wide ? (o32 ? k_collide_row<QH, T, FS, GS, true, 512> : k_collide_row<QH, T, FS, GS, false, 512>)
-                      : (o32 ? k_collide_row<QH, T, FS, GS, true, NT> : k_collide_row<QH, T, FS, GS, false, NT>);
+        const bool one = wide && c->p.nx == 512;   // one cell per thread
+        auto k = one ? (o32 ? k_collide_row<QH, T, FS, GS, true, 512, true>
+                            : k_collide_row<QH, T, FS, GS, false, 512, true>)
+                 : wide ? (o32 ? k_collide_row<QH, T, FS, GS, true, 512> : k_collide_row<QH, T, FS, GS, false, 512>)
+                        : (o32 ? k_collide_row<QH, T, FS, GS, true, NT> : k_collide_row<QH, T, FS, GS, false, NT>);
         const unsigned lds = xrow_bytes<DIM, QH, FS, GS>(c->p.nx);
         Timed tm(c, 2);
         hipLaunchKernelGGL(k, dim3((unsigned)(c->p.ny * c->p.nz)), dim3(wide ? 512 : NT), lds, c->stream, planes(c), (const T*)c->phi(),
