@@ -382,13 +382,14 @@ def test_conservation(dim, q):
     assert d1["finite"] and d1["nci_active"] > 0
 
 
-def _laplace_ratio(Wd):
+def _laplace_ratio(Wd, density_ratio=1.0):
     """Time-averaged (p_in - p_out) R / sigma for a static droplet with R = 3 W in a box of
     16 W: acoustic modes of the periodic box are barely damped at tau = 1, so the jump is
     averaged over 2000 W/4 steps after a 500 W/4 step start-up."""
     s = Wd / 4.0
     N, R = int(64 * s), 12.0 * s
-    p = W.Params(dim=2, nx=N, ny=N, tau=1.0, sigma=1e-3, a_rep=0.0, width=Wd)
+    p = W.Params(dim=2, nx=N, ny=N, tau=1.0, sigma=1e-3, a_rep=0.0, width=Wd,
+                 density_ratio=density_ratio)
     st = W.static_droplet(p, R)
     o = O.Oracle(p)
     o.init_fields(st.phi, st.u)
@@ -414,6 +415,171 @@ def test_laplace_law_and_spurious_currents():
     assert abs(r8 - 1) < 0.02
     assert abs(r8 - 1) < abs(r4 - 1) / 3.5
     assert u4 < 1e-5 and u8 < 1e-5
+
+
+def test_laplace_law_at_density_ratio_10():
+    """The same static droplet at rho_l / rho_g = 10 (Sec. 2.1, "Mixture properties" and
+    "Forcing scheme").  Only the pressure p = rho cs^2 p* jumps by sigma / R: the hydrodynamic
+    populations carry p*, and the pressure-gradient correction F_p = -p* cs^2 grad rho of
+    Eq. Fp turns grad p* into grad p / rho.  Measured: 0.966 at W = 4 and 0.994 at W = 8.  A
+    sign slip in F_p gives 2.98 at W = 4, and dropping it gives 2.06."""
+    r4, u4 = _laplace_ratio(4.0, density_ratio=10.0)
+    r8, u8 = _laplace_ratio(8.0, density_ratio=10.0)
+    assert abs(r4 - 1) < 0.08
+    assert abs(r8 - 1) < abs(r4 - 1) / 3.0
+    assert u4 < 1e-5 and u8 < 1e-5
+
+
+# ---------------------------------------------------------------------------
+# Variable density and viscosity with a body force (Sec. 2.1: Eqs. mu_mix_linear,
+# nu_from_mu, omega_phi, Fsplit, Fp, Fnu; the body force of the swarm section)
+# ---------------------------------------------------------------------------
+
+def _layers(Wd, L, ratio, visc_ratio, g, tau=1.0):
+    """A liquid layer of thickness L/2 normal to y in an L-periodic box one cell wide
+    (x), the gas layer filling the rest; g = (g_x, g_y)."""
+    p = W.Params(dim=2, nx=1, ny=L, tau=tau, sigma=1e-3, a_rep=0.0, width=Wd,
+                 density_ratio=ratio, visc_ratio=visc_ratio, body_force=(g[0], g[1], 0.0))
+    return p, W.slab(p, L / 2, axis=1)
+
+
+def _counterflow_diffuse(L, Wd, ratio, nu_l, nu_g, g, sub=64):
+    """Steady solution of the x-momentum balance d/dy(mu du/dy) = -(rho - rho_mean) g of
+    parallel flow, for the continuous profile phi = (1 + tanh(2 s / W)) / 2 of the layer
+    (s the distance to the interface, positive in the liquid), with the linear mixture
+    rules rho = rho_g + (rho_l - rho_g) phi and mu = rho_g nu_g + (rho_l nu_l - rho_g nu_g) phi
+    (Eq. mu_mix_linear).  Shear stress tau = mu u' = C - int_0^y f; C from periodicity of u
+    (int u' = 0).  Trapezoid quadrature on `sub` points per cell; u at the nodes, mean
+    removed (parallel flow leaves the velocity defined up to a constant)."""
+    M = L * sub
+    y = np.arange(M + 1) / sub
+    c = (L - 1) / 2.0
+    d = np.abs(y - c)
+    d = np.minimum(d, L - d)
+    phi = 0.5 * (1.0 + np.tanh(2.0 * (L / 4.0 - d) / Wd))
+    rg = 1.0 / ratio
+    rho = rg + (1.0 - rg) * phi
+    mu = rg * nu_g + (nu_l - rg * nu_g) * phi
+    rho_mean = rho[:-1].mean()
+    f = (rho - rho_mean) * g
+    h = 1.0 / sub
+    trap = lambda v: np.concatenate([[0.0], np.cumsum(0.5 * (v[1:] + v[:-1]) * h)])
+    Fi = trap(f)
+    C = trap(Fi / mu)[-1] / trap(1.0 / mu)[-1]
+    u = trap((C - Fi) / mu)[::sub][:-1]
+    return u - u.mean()
+
+
+def _counterflow_sharp(L, ratio, nu_l, nu_g, g):
+    """The same balance for sharp interfaces at y = c +- L/4: constant rho, mu in each layer,
+    u piecewise parabolic, u' = 0 at both layer centres, mu u' continuous."""
+    rg = 1.0 / ratio
+    rho_mean = (1.0 + rg) / 2.0
+    fl, fg = (1.0 - rho_mean) * g, (rg - rho_mean) * g
+    ml, mg = nu_l, rg * nu_g
+    h = L / 4.0
+    y = np.arange(L, dtype=np.float64)
+    d = np.abs(y - (L - 1) / 2.0)
+    d = np.minimum(d, L - d)
+    s = d - h
+    u = np.where(d <= h, -fl * d * d / (2 * ml),
+                 -fl * h * h / (2 * ml) - (fl * h * s + 0.5 * fg * s * s) / mg)
+    return u - u.mean()
+
+
+def _counterflow(Wd, L, visc_ratio, g=1e-7, tau=1.0, max_steps=200000):
+    """Steady x-velocity profile of the oracle (mean removed) and the two references."""
+    p, st = _layers(Wd, L, 10.0, visc_ratio, (g, 0.0), tau)
+    o = O.Oracle(p)
+    o.init_fields(st.phi)
+    nu_l = (tau - 0.5) / 3.0
+    ref = _counterflow_diffuse(L, Wd, 10.0, nu_l, visc_ratio * nu_l, g)
+    sharp = _counterflow_sharp(L, 10.0, nu_l, visc_ratio * nu_l, g)
+    prev = None
+    while o.step_count < max_steps:
+        o.step(1000)
+        u = o.u()[0][:, 0]
+        u = u - u.mean()
+        if prev is not None and np.abs(u - prev).max() < 1e-5 * np.abs(ref).max():
+            break
+        prev = u
+    assert o.step_count < max_steps, "no steady state"
+    assert np.abs(o.u()[1]).max() < 1e-6       # parallel flow: no normal velocity
+    err = np.abs(u - ref).max() / np.abs(ref).max()
+    err_sharp = np.abs(u - sharp).max() / np.abs(sharp).max()
+    return err, err_sharp
+
+
+def test_two_layer_counterflow_variable_viscosity():
+    """Periodic liquid / gas layers at density ratio 10 driven along the layers by
+    F_ext = (rho - <rho>) g (net force zero, so the layers slide past each other).  The
+    steady profile must solve d/dy(mu du/dy) = -(rho - <rho>) g, which holds only if the
+    lattice viscosity nu(phi) = mu(phi) / rho(phi) (Eqs. mu_mix_linear, nu_from_mu,
+    omega_phi) and the viscous correction F_nu (Eq. Fnu) together give the divergence of
+    mu (grad u + grad u^T).  Against the quadrature of that balance on the equilibrium
+    tanh profile, the error falls at second order in 1/W at fixed W / L (measured: 1.8 % and
+    0.42 % at visc_ratio 0.1; 5.3 % and 1.3 % at visc_ratio 10, where the dynamic viscosities
+    are equal).  Against the sharp-interface piecewise parabola the error falls with W / L
+    (first order: the diffuse interface, where mu is mixed linearly, thins the less viscous
+    layer).  Planted faults fail by far: F_nu with the wrong sign (69 %, 450 %), F_nu
+    dropped (29 %, 240 %), kinematic instead of dynamic viscosity mixing (21 %, 23 %),
+    visc_ratio read as nu_l / nu_g (98 %), F_ext with the wrong sign (200 %)."""
+    e4, s4 = _counterflow(4.0, 64, 0.1)
+    e8, s8 = _counterflow(8.0, 128, 0.1)
+    assert e4 < 0.025 and e8 < e4 / 3.5
+    f4, t4 = _counterflow(4.0, 64, 10.0)
+    f8, t8 = _counterflow(8.0, 128, 10.0)
+    assert f4 < 0.06 and f8 < f4 / 3.5
+    assert t4 < 0.07 and t8 < 0.03                  # equal mu: close to the sharp parabola
+    # sharp-interface limit at visc_ratio 0.1: halving W / L halves the error
+    _, s4b = _counterflow(4.0, 128, 0.1)
+    assert 0.35 < s4 < 0.45 and s4b < 0.6 * s4
+
+
+def test_hydrostatic_layers_with_gravity_normal_to_them():
+    """The same layers at rest with gravity g = -1e-6 y normal to them (density ratio 10):
+    the pressure p = rho cs^2 p* must be hydrostatic, grad p = (rho - <rho>) g, in the bulk
+    of both layers and across the interfaces, i.e. p(y) - p(0) equals the integral of
+    (rho - <rho>) g_y along y (the capillary force of a flat interface integrates to zero).
+    Averaged over 1000 W/4 steps to remove the box's acoustic modes.  Measured: 6.9 % of
+    the hydrostatic pressure range at W = 4, 0.4 % at W = 8.  The fluid is at rest up to a
+    uniform drift: the p* formulation conserves sum u + F/(2 rho) - sum F/rho, not sum rho u,
+    and the discrete product rule of F_p leaves a net acceleration of 2 % of g at W = 4 that
+    falls at second order in 1/W.  Planted faults: F_p with the wrong sign (268 %), F_p
+    dropped (158 %), F_ext with the wrong sign (57 %), F_ext = rho g (43 %)."""
+    res = {}
+    for Wd, L in ((4.0, 64), (8.0, 128)):
+        s = Wd / 4.0
+        g = 1e-6
+        p, st = _layers(Wd, L, 10.0, 1.0, (0.0, -g))
+        o = O.Oracle(p)
+        o.init_fields(st.phi)
+        steps, avg = int(3000 * s), int(1000 * s)
+        o.step(steps - avg)
+        rg = 1.0 / p.density_ratio
+        rho_mean = rg + (1.0 - rg) * st.phi.mean()
+        d = np.abs(np.arange(L) - (L - 1) / 2.0)
+        d = np.minimum(d, L - d)
+        bulk = np.abs(d - L / 4.0) > 2 * Wd
+        dev, us, span = [], [], 0.0
+        while o.step_count < steps:
+            o.step(10)
+            rho = o.rho()[:, 0]
+            pr = rho * o.pstar()[:, 0] / 3.0
+            f = (rho - rho_mean) * (-g)
+            hyd = np.concatenate([[0.0], np.cumsum(0.5 * (f[1:] + f[:-1]))])
+            span = hyd.max() - hyd.min()
+            dev.append(pr - hyd)
+            us.append(o.u()[1][:, 0])
+        e = np.mean(dev, axis=0)
+        e = e - e[bulk].mean()
+        u = np.mean(us, axis=0)
+        res[Wd] = (np.abs(e[bulk]).max() / span, u.mean() / steps, np.abs(u - u.mean()).max())
+        assert np.abs(o.u()[0]).max() < 1e-12          # nothing along the layers
+    (e4, a4, d4), (e8, a8, d8) = res[4.0], res[8.0]
+    assert e4 < 0.08 and e8 < 0.01
+    assert d4 < 1e-6 and d8 < 1e-6                       # no flow relative to the drift
+    assert abs(a4) < 0.03 * 1e-6 and abs(a8) < abs(a4) / 3.0
 
 
 def test_advection_returns_droplet():
@@ -562,6 +728,50 @@ def test_partner_rule_edges_and_ties():
     put(q, n, (8, 12), 0.2, (-1.0, 0.0))          # |dx| = 4 > w
     chi, part, J = _grid(base, q, n)
     assert chi.sum() == 0 and np.all(J == 0) and np.all(part == 0)
+
+
+def test_partner_tie_band():
+    """The tie band of the partner rule (Sec. 2.3.2, reading R16): among the accepted
+    candidates at the smallest |r|^2, facing scores within tie_eps of the best are tied and
+    the first of them in scan order (dz, dy, dx from -w) wins; one beyond tie_eps loses to
+    the best; the band is measured from the best, not chained from candidate to candidate."""
+    base = W.Params(dim=2, nx=16, ny=16, a_rep=1.0, q_th=0.125, eta=0.125, cos_opp=-0.75,
+                    width=4.0, tie_eps=1e-6)
+    x0 = (8, 8)
+
+    def case(dots):
+        """dots: {(dx, dy): n(x).n(y)} for candidates at |r|^2 = 1; n(x) = (1, 0)."""
+        q = np.zeros(base.shape)
+        n = np.zeros((2,) + base.shape)
+        q[x0] = 0.2
+        n[0][x0] = 1.0
+        for (dx, dy), dot in dots.items():
+            yx = (x0[0] + dy, x0[1] + dx)
+            q[yx] = 0.2
+            n[0][yx], n[1][yx] = dot, math.sqrt(1.0 - dot * dot)
+        chi, part, _ = _grid(base, q, n)
+        assert chi[x0] == 1
+        return int(part[0][x0]), int(part[1][x0])
+
+    # scan order of the |r|^2 = 1 candidates: (0, -1), (-1, 0), (1, 0), (0, 1)
+    assert case({(0, -1): -0.9 + 0.5e-6, (0, 1): -0.9}) == (0, -1)      # inside the band
+    assert case({(0, -1): -0.9 + 2e-6, (0, 1): -0.9}) == (0, 1)         # beyond it
+    assert case({(1, 0): -0.9 + 0.5e-6, (-1, 0): -0.9}) == (-1, 0)      # best is also first
+    # not chained: (0, -1) is 1.6e-6 from the best (0, 1) though 0.8e-6 from (1, 0)
+    assert case({(0, -1): -0.9 + 1.6e-6, (1, 0): -0.9 + 0.8e-6, (0, 1): -0.9}) == (1, 0)
+    # the band only ties equal distances: a nearer candidate with a worse score still wins
+    q = np.zeros(base.shape)
+    n = np.zeros((2,) + base.shape)
+    q[x0] = 0.2
+    n[0][x0] = 1.0
+    for (dx, dy), dot in {(1, 1): -0.9, (0, 1): -0.9 + 0.5e-6}.items():
+        q[x0[0] + dy, x0[1] + dx] = 0.2
+        n[0][x0[0] + dy, x0[1] + dx], n[1][x0[0] + dy, x0[1] + dx] = dot, math.sqrt(1 - dot * dot)
+    chi, part, _ = _grid(base, q, n)
+    assert (int(part[0][x0]), int(part[1][x0])) == (0, 1)
+    # tie_eps = 0 restores the strict largest facing score
+    base = base.replace(tie_eps=0.0)
+    assert case({(0, -1): -0.9 + 0.5e-6, (0, 1): -0.9}) == (0, 1)
 
 
 def test_repulsive_flux_value_and_orientation():
