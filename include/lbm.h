@@ -218,10 +218,23 @@ int lbm_set_populations(lbm_ctx* ctx, const double* f, const double* g);
 
 /* Raw state (populations in their stored precision and AA layout, step count;
  * with cac_solver 1 also phi) for checkpoint / restart; a restored context
- * continues bit for bit. */
+ * continues bit for bit.  The header records a format version, the box, the
+ * precision, the hydrodynamic lattice and the phase-field solver:
+ * lbm_load_state returns LBM_E_INVALID unless all of them equal the context's
+ * and bytes equals lbm_state_bytes(ctx).  lbm_save_state needs at least
+ * lbm_state_bytes(ctx) bytes. */
 size_t lbm_state_bytes(const lbm_ctx* ctx);
 int lbm_save_state(lbm_ctx* ctx, void* host_buf, size_t bytes);
 int lbm_load_state(lbm_ctx* ctx, const void* host_buf, size_t bytes);
+
+/* Testing hook: on != 0 makes the context's collide launches (k_collide,
+ * k_collide_row, and k_collide_multi in every batch that holds the context)
+ * use the instantiations that form element offsets in 64 bits, which a box
+ * needs once a z plane of populations or a phi plane reaches 4 GiB (e.g. the
+ * 1024^3 swarm).  The arithmetic is the same; this lets those kernels be
+ * checked on boxes the oracle can step.  Synchronises the context's stream.
+ * Returns LBM_OK or LBM_E_INVALID / LBM_E_HIP. */
+int lbm_force_wide_offsets(lbm_ctx* ctx, int on);
 
 /* Serving: advance every context by n steps of the coupled update (Sec. 2,
  * the step lbm_step performs) with multi-domain launches that cover all of

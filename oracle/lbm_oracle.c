@@ -460,6 +460,16 @@ int oracle_threads(void) {
 #endif
 }
 
+int oracle_set_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+  return omp_get_max_threads();
+#else
+  (void)n;
+  return 1;
+#endif
+}
+
 static long nb(const oracle_state* s, long idx, const int* c) {
   long x = idx % s->nx, y = (idx / s->nx) % s->ny, z = idx / (s->nx * s->ny);
   return wrapi(x + c[0], s->nx) + s->nx * (wrapi(y + c[1], s->ny) + s->ny * wrapi(z + c[2], s->nz));
@@ -808,6 +818,12 @@ int oracle_set_populations(oracle_state* s, const double* f, const double* g) {
 /* Test knob: the reference density of the buoyancy force, F_ext = (rho - rho_mean) g,
  * is the box mean at initialisation; a sub-box cut from a larger periodic box takes
  * the larger box's value instead. */
+int oracle_set_phi(oracle_state* s, const double* phi) {
+  if (!s || !phi || s->P.cac_solver == 0) return -1;   /* phi is state only in MUSCL mode */
+  for (long idx = 0; idx < s->N; ++idx) s->phi[idx] = phi[idx];
+  return 0;
+}
+
 int oracle_set_rho_mean(oracle_state* s, double rho_mean) {
   if (!s) return -1;
   s->rho_mean = rho_mean;

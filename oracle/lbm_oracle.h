@@ -61,6 +61,8 @@ int oracle_lattice(int kind, int* q, int* c, double* w, double* cs2);
 oracle_state* oracle_create(const oracle_params* p);
 void oracle_destroy(oracle_state* s);
 int oracle_threads(void);
+/* OpenMP threads of later calls (n > 0); returns the count now in effect. */
+int oracle_set_threads(int n);
 
 /* phi, pstar: N doubles or NULL (pstar NULL => 0); u: dim*N SoA or NULL (=> 0). */
 int oracle_init_fields(oracle_state* s, const double* phi, const double* u, const double* pstar);
@@ -69,6 +71,10 @@ int oracle_set_populations(oracle_state* s, const double* f, const double* g);
 /* Test knob: override the reference density rho_mean of F_ext = (rho - rho_mean) g
  * (by default the box mean at initialisation), for a sub-box of a larger box. */
 int oracle_set_rho_mean(oracle_state* s, double rho_mean);
+/* Test knob for the finite-difference phase field (cac_solver 1), whose state is f and
+ * phi: replace phi (N doubles).  -1 for the lattice Boltzmann phase field, where phi is
+ * the moment of g. */
+int oracle_set_phi(oracle_state* s, const double* phi);
 int oracle_get_populations(const oracle_state* s, double* f, double* g);
 int oracle_step(oracle_state* s, int n);
 long oracle_step_count(const oracle_state* s);

@@ -58,10 +58,13 @@ def load():
     lib.oracle_create.argtypes = [C.POINTER(_Params)]
     lib.oracle_destroy.argtypes = [vp]
     lib.oracle_threads.restype = C.c_int
+    lib.oracle_set_threads.restype = C.c_int
+    lib.oracle_set_threads.argtypes = [C.c_int]
     for name in ("oracle_init_fields",):
         getattr(lib, name).argtypes = [vp, dp, dp, dp]
     lib.oracle_set_populations.argtypes = [vp, dp, dp]
     lib.oracle_set_rho_mean.argtypes = [vp, C.c_double]
+    lib.oracle_set_phi.argtypes = [vp, dp]
     lib.oracle_get_populations.argtypes = [vp, dp, dp]
     lib.oracle_step.argtypes = [vp, C.c_int]
     lib.oracle_step_count.restype = C.c_long
@@ -178,6 +181,13 @@ class Oracle:
     def set_rho_mean(self, rho_mean: float):
         """Reference density of the buoyancy force for a sub-box of a larger box."""
         self.lib.oracle_set_rho_mean(self.h, float(rho_mean))
+
+    def set_phi(self, phi):
+        """Finite-difference phase field only: replace the stored phi."""
+        phi = np.ascontiguousarray(phi, dtype=np.float64).reshape(-1)
+        assert phi.size == self.N
+        if self.lib.oracle_set_phi(self.h, _dptr(phi)):
+            raise RuntimeError("oracle_set_phi needs cac_solver = 1")
 
     def get_populations(self):
         f = np.zeros(self.qf * self.N)

@@ -179,6 +179,7 @@ struct lbm_ctx {
   double k_ms[5] = {0, 0, 0, 0, 0};
   long k_cnt[5] = {0, 0, 0, 0, 0};
   int phi_cur = 0;   // finite-difference phase field: which phi buffer holds the state
+  bool wide_offsets = false;   // lbm_force_wide_offsets: 64-bit offset kernels at any size
 
   void* f() const { return ws + L.off_f; }
   void* g() const { return ws + L.off_g; }
@@ -389,8 +390,10 @@ struct Engine {
   }
 
   // 32-bit byte offsets are used when the populations of a z plane and every
-  // phi / J plane stay below 4 GiB.
+  // phi / J plane stay below 4 GiB (and lbm_force_wide_offsets has not asked
+  // for the 64-bit kernels).
   static bool off32(const lbm_ctx* c) {
+    if (c->wide_offsets) return false;
     const size_t plane = (size_t)c->p.nx * c->p.ny;
     const size_t widest = std::max(plane * HydroQ<QH>::Q * sizeof(FS),
                                    std::max(plane * Phase<DIM>::Q * sizeof(GS), (size_t)c->L.S * sizeof(T)));
@@ -726,6 +729,28 @@ struct Engine {
                          st, dj, nj, s);
   }
 
+  // Table entry of one lattice whose blocks start at blk0 of the batch grid.
+  static JobT job_entry(lbm_ctx* c, int blk0) {
+    JobT jb{};
+    jb.pl = planes(c);
+    jb.phi = (T*)c->phi();
+    jb.J = (T*)c->J();
+    for (int k = 0; k < 2; ++k) {
+      jb.flags[k] = c->flags(k);
+      jb.list[k] = c->list(k);
+    }
+    jb.cnt = c->cnt();
+    jb.geo = c->geo;
+    jb.pp = physT(c);
+    jb.np = c->nci;
+    jb.nci_on = c->nci_on() ? 1 : 0;
+    jb.q_th = (T)c->p.q_th;
+    jb.blk0 = blk0;
+    jb.nblk = c->L.nblk;
+    jb.step = c->step;
+    return jb;
+  }
+
   static int batch(lbm_ctx* const* cs, int count, int n) {
     lbm_ctx* c0 = cs[0];
     hipStream_t st = c0->stream;
@@ -757,27 +782,9 @@ struct Engine {
     int blocks = 0;
     bool o32 = true;
     for (int i = 0; i < count; ++i) {
-      lbm_ctx* c = cs[i];
-      JobT jb{};
-      jb.pl = planes(c);
-      jb.phi = (T*)c->phi();
-      jb.J = (T*)c->J();
-      for (int k = 0; k < 2; ++k) {
-        jb.flags[k] = c->flags(k);
-        jb.list[k] = c->list(k);
-      }
-      jb.cnt = c->cnt();
-      jb.geo = c->geo;
-      jb.pp = physT(c);
-      jb.np = c->nci;
-      jb.nci_on = c->nci_on() ? 1 : 0;
-      jb.q_th = (T)c->p.q_th;
-      jb.blk0 = blocks;
-      jb.nblk = c->L.nblk;
-      jb.step = c->step;
-      blocks += c->L.nblk;
-      o32 = o32 && off32(c);
-      hj[i] = jb;
+      hj[i] = job_entry(cs[i], blocks);
+      blocks += cs[i]->L.nblk;
+      o32 = o32 && off32(cs[i]);
     }
     HIP_OR_FAIL(c0, hipMemcpyAsync(B->djobs, B->hjobs, B->bytes, hipMemcpyHostToDevice, st));
     HIP_OR_FAIL(c0, hipEventRecord(B->copied, st));
@@ -1183,16 +1190,24 @@ int lbm_set_populations(lbm_ctx* c, const double* f, const double* g) {
   return LBM_OK;
 }
 
-// Raw state: header {magic, step, rho_mean, dispersed} + f + g as stored.
+// Raw state: header {magic, format version, step, rho_mean, dispersed, box,
+// precision, lattice, phase-field solver} + f + g as stored (+ phi with the
+// finite-difference phase field).
 namespace {
 struct StateHeader {
   unsigned long long magic;
+  long long version;
   long long step;
   double rho_mean;
   long long dispersed;
-  long long nx, ny, nz, precision;
+  long long dim, nx, ny, nz, precision, hydro_q, cac_solver;
 };
 constexpr unsigned long long STATE_MAGIC = 0x4c424d5354415445ULL;  // "LBMSTATE"
+constexpr long long STATE_VERSION = 2;
+StateHeader state_header(const lbm_ctx* c) {
+  return StateHeader{STATE_MAGIC, STATE_VERSION, c->step, c->phys.rho_mean, c->dispersed, c->p.dim,
+                     c->p.nx, c->p.ny, c->p.nz, c->p.precision, q_hydro(&c->p), c->p.cac_solver};
+}
 size_t pop_bytes(const lbm_ctx* c) {
   return c->L.off_phi;  // f and g are the first two regions of the workspace
 }
@@ -1209,8 +1224,7 @@ size_t lbm_state_bytes(const lbm_ctx* c) {
 int lbm_save_state(lbm_ctx* c, void* buf, size_t bytes) {
   NEED_INIT(c);
   if (!buf || bytes < lbm_state_bytes(c)) return c->fail(LBM_E_INVALID, "state buffer too small");
-  StateHeader h{STATE_MAGIC, c->step, c->phys.rho_mean, c->dispersed, c->p.nx, c->p.ny, c->p.nz,
-                c->p.precision};
+  const StateHeader h = state_header(c);
   std::memcpy(buf, &h, sizeof(h));
   HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
   HIP_OR_FAIL(c, hipMemcpy((char*)buf + sizeof(h), c->ws, pop_bytes(c), hipMemcpyDeviceToHost));
@@ -1222,12 +1236,16 @@ int lbm_save_state(lbm_ctx* c, void* buf, size_t bytes) {
 
 int lbm_load_state(lbm_ctx* c, const void* buf, size_t bytes) {
   if (!c) return LBM_E_INVALID;
-  if (!buf || bytes < lbm_state_bytes(c)) return c->fail(LBM_E_INVALID, "state buffer too small");
+  if (!buf || bytes != lbm_state_bytes(c))
+    return c->fail(LBM_E_INVALID, "state size does not match this context");
   StateHeader h;
   std::memcpy(&h, buf, sizeof(h));
-  if (h.magic != STATE_MAGIC || h.nx != c->p.nx || h.ny != c->p.ny || h.nz != c->p.nz ||
-      h.precision != c->p.precision)
-    return c->fail(LBM_E_INVALID, "state does not match this context");
+  const StateHeader want = state_header(c);
+  if (h.magic != STATE_MAGIC || h.version != STATE_VERSION)
+    return c->fail(LBM_E_INVALID, "not a state of this library version");
+  if (h.dim != want.dim || h.nx != want.nx || h.ny != want.ny || h.nz != want.nz ||
+      h.precision != want.precision || h.hydro_q != want.hydro_q || h.cac_solver != want.cac_solver)
+    return c->fail(LBM_E_INVALID, "state does not match this context (box, precision, lattice or solver)");
   HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
   HIP_OR_FAIL(c, hipMemcpy(c->ws, (const char*)buf + sizeof(h), pop_bytes(c), hipMemcpyHostToDevice));
   c->phi_cur = 0;
@@ -1241,6 +1259,13 @@ int lbm_load_state(lbm_ctx* c, const void* buf, size_t bytes) {
   HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
   c->hist_count = 0;
   c->initialised = true;
+  return LBM_OK;
+}
+
+int lbm_force_wide_offsets(lbm_ctx* c, int on) {
+  if (!c) return LBM_E_INVALID;
+  HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+  c->wide_offsets = on != 0;
   return LBM_OK;
 }
 
@@ -1272,11 +1297,12 @@ int lbm_kernel_times(lbm_ctx* c, double* ms, long* counts) {
   return LBM_OK;
 }
 
-int lbm_batch_step(lbm_ctx* const* ctxs, int count, int n) {
-  if (!ctxs || count < 0 || n < 0) return LBM_E_INVALID;
-  if (count == 0 || n == 0) return LBM_OK;
+}  // extern "C"
+
+namespace {
+// Checks shared by the batch entry points; LBM_OK when the list may be stepped.
+int check_batch(lbm_ctx* const* ctxs, int count) {
   lbm_ctx* c0 = ctxs[0];
-  if (!c0) return LBM_E_INVALID;
   for (int i = 0; i < count; ++i) {
     lbm_ctx* c = ctxs[i];
     if (!c) return c0->fail(LBM_E_INVALID, "null context in batch");
@@ -1289,6 +1315,19 @@ int lbm_batch_step(lbm_ctx* const* ctxs, int count, int n) {
     for (int j = 0; j < i; ++j)
       if (ctxs[j] == c) return c0->fail(LBM_E_INVALID, "context listed twice in batch");
   }
+  return LBM_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int lbm_batch_step(lbm_ctx* const* ctxs, int count, int n) {
+  if (!ctxs || count < 0 || n < 0) return LBM_E_INVALID;
+  if (count == 0 || n == 0) return LBM_OK;
+  lbm_ctx* c0 = ctxs[0];
+  if (!c0) return LBM_E_INVALID;
+  const int rc = check_batch(ctxs, count);
+  if (rc != LBM_OK) return rc;
   return dispatch(c0, [&](auto E) { return decltype(E)::batch(ctxs, count, n); });
 }
 

@@ -69,6 +69,14 @@ def load():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'`")
+    # One HIP runtime per process: torch's libraries ask for libamdhip64.so by its
+    # file name, which a runtime loaded earlier under its versioned name does not
+    # satisfy, so loading the library first would leave two runtimes that cannot
+    # share the device.  With torch imported first, the library binds to torch's.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = C.CDLL(LIB_PATH)
     vp, dp, ip = C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int)
     P = C.POINTER(lbm_params)
@@ -104,6 +112,7 @@ def load():
     lp = C.POINTER(C.c_long)
     lib.lbm_curvature_histogram.argtypes = [vp, C.c_double, C.c_double, C.c_double, C.c_int, lp]
     lib.lbm_component_volumes.argtypes = [vp, lp, C.c_long, lp]
+    lib.lbm_force_wide_offsets.argtypes = [vp, C.c_int]
     _lib = lib
     return lib
 
@@ -315,6 +324,10 @@ class Lattice:
             raise LBMError(-1, f"{n.value} components, more than max_count = {max_count}")
         return out[: n.value].copy()
 
+    def force_wide_offsets(self, on: bool = True):
+        """Testing hook: run the collide kernels with 64-bit element offsets."""
+        self._check(self.lib.lbm_force_wide_offsets(self.h, 1 if on else 0))
+
     def kernel_times(self):
         """{kernel: (total_ms, launches)} since the last call (synchronises)."""
         ms = np.zeros(5)
@@ -343,3 +356,4 @@ def lbm_batch_step(lattices: Sequence[Lattice], n: int):
     rc = lib.lbm_batch_step(arr, len(lattices), int(n))
     if rc < 0:
         raise LBMError(rc, lib.lbm_last_error(lattices[0].h).decode())
+

@@ -1,6 +1,11 @@
 """Shared test helpers: error norms and the mapping between the population
 orders of the GPU library and of the oracle (matched by velocity vector)."""
+import json
+import os
+
 import numpy as np
+
+ENVELOPES = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "roundoff_envelopes.json")
 
 
 def rel_linf(a, b):
@@ -67,3 +72,10 @@ def roundoff_envelope(st, steps, fields, kind="fp64", seed=0):
     a.step(steps)
     b.step(steps)
     return {f: rel_linf(getattr(b, f)(), getattr(a, f)()) for f in fields}
+
+
+def stored_envelope(key):
+    """The oracle's rounding envelope of a head-on collision case, as written by
+    tests/golden/make_envelopes.py (roundoff_envelope above, run on the oracle)."""
+    with open(ENVELOPES) as fh:
+        return json.load(fh)[key]

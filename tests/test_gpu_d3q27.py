@@ -14,7 +14,8 @@ from oracle.oracle import Oracle
 from paper_2603_17481_amd import lbm as L
 from paper_2603_17481_amd import serving as S
 from paper_2603_17481_amd import workloads as W
-from tests.helpers import announce, near_contact_pair, rel_linf, roundoff_envelope, velocity_permutation
+from tests.helpers import (announce, near_contact_pair, rel_linf, roundoff_envelope, stored_envelope,
+                           velocity_permutation)
 
 pytestmark = pytest.mark.gpu
 
@@ -71,7 +72,7 @@ def test_fp64_collision_envelope_and_tiny_box():
     assert_fields(g, o, FP64_BAR)
     g.step(30)
     o.step(30)
-    env = roundoff_envelope(st, 40, ("phi", "u"))
+    env = stored_envelope("collision_3d_d3q27_fp64_40")
     print(f"[gpu-case] envelope {env}", flush=True)
     assert_fields(g, o, {f: max(FP64_BAR, 10 * env[f]) for f in env}, fields=("phi", "u"))
     p3 = W.Params(dim=3, nx=9, ny=7, nz=5, width=3.0, sigma=5e-3, a_rep=5e-3, density_ratio=10.0,

@@ -1,0 +1,396 @@
+"""Oracle parity of the paths that the full-size workloads take and the short
+tests above do not reach.
+
+  * the collide kernels with 64-bit element offsets (k_collide, k_collide_row,
+    k_collide_multi instantiated with OFF32 = false), which every box needs once
+    a z plane of populations or a phi plane reaches 4 GiB (the 1024^3 swarm):
+    forced on small boxes with the lbm_force_wide_offsets testing hook, FP64
+    against the oracle at 1e-12 after 100 steps;
+  * the 1024^3 FP16-storage swarm (20000 bubbles, radii U[6, 10], gap 2) in the
+    launch configuration the benchmark uses, one step of each AA parity on
+    sampled sub-boxes (the locality argument of test_gpu_fullsize);
+  * the finite-difference phase field's z-marching kernel over several 64-plane
+    chunks (nz = 150), and in the 512^3 sub-box test;
+  * lattices advanced inside lbm_batch_step, each against the oracle;
+  * FP16 / BF16 storage through the odd parity's row kernel (nx >= 256), one step
+    against the oracle at the storage format's rounding, and 100 steps within the
+    envelope of the oracle whose stored populations are rounded to that format.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from oracle.oracle import Oracle
+from paper_2603_17481_amd import lbm as L
+from paper_2603_17481_amd import serving as S
+from paper_2603_17481_amd import workloads as W
+from tests.helpers import announce, near_contact_pair, rel_linf, roundoff_envelope, velocity_permutation
+
+pytestmark = pytest.mark.gpu
+
+FP64_BAR = 1e-12
+FP32_BAR = 1e-5
+FIELDS = ("phi", "rho", "u", "pstar")
+
+
+def errors(g, o, fields=FIELDS):
+    return {f: rel_linf(getattr(g, f)(), getattr(o, f)()) for f in fields}
+
+
+def wide_box(precision="fp64", nx=320, **kw):
+    st = near_contact_pair(3, precision, nx=nx)
+    return W.InitialState(st.params.replace(**kw), st.phi, st.u, st.spheres, st.kind)
+
+
+def perms(dim, hq):
+    if dim == 2:
+        return (velocity_permutation(L.lbm_lattice(2, 0), O.lattice(0)[0]),
+                velocity_permutation(L.lbm_lattice(2, 1), O.lattice(0)[0]))
+    return (velocity_permutation(L.lbm_lattice(3, 0 if hq == 19 else 2), O.lattice(1 if hq == 19 else 3)[0]),
+            velocity_permutation(L.lbm_lattice(3, 1), O.lattice(2)[0]))
+
+
+# ---------------------------------------------------------------------------
+# 64-bit element offsets
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("dim,hq,solver,steps", [(3, 19, 0, 100), (3, 27, 0, 30), (3, 19, 1, 60), (2, 9, 0, 100)])
+def test_wide_offset_kernels_fp64_match_oracle(dim, hq, solver, steps):
+    """320-wide 3D box: the even parity runs k_collide, the odd parity k_collide_row,
+    both with 64-bit offsets; 2D: k_collide."""
+    st = wide_box(hydro_q=hq, cac_solver=solver) if dim == 3 else near_contact_pair(2)
+    p = st.params
+    announce(f"wide offsets {dim}D D{dim}Q{hq} solver={solver} {p.nx}x{p.ny}x{p.nz} steps={steps}")
+    g = L.Lattice(p)
+    g.force_wide_offsets(True)
+    g.init_fields(st.phi, st.u)
+    g.step(steps)
+    g.sync()
+    o = Oracle(p)
+    o.init_fields(st.phi, st.u)
+    o.step(steps)
+    errs = errors(g, o)
+    print(f"[gpu-case] errors {errs}", flush=True)
+    assert all(v <= FP64_BAR for v in errs.values()), errs
+    chi_g, part_g, _ = g.nci()
+    chi_o, part_o, _ = o.nci()
+    assert chi_o.sum() > 0 and np.array_equal(chi_g, chi_o) and np.array_equal(part_g, part_o)
+    g.close()
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp16"])
+def test_wide_offsets_batch_equals_alone(precision):
+    """A batch that holds a context with wide offsets runs k_collide_multi<OFF32 =
+    false> for all of its lattices; each ends bit for bit where lbm_step (wide
+    offsets on) leaves it, and where the 32-bit kernels leave it."""
+    states = [wide_box(precision), near_contact_pair(3, precision, nx=56)]
+    announce(f"wide offsets batch {precision}")
+
+    def build(wide):
+        out = []
+        for st in states:
+            g = L.Lattice(st.params)
+            g.init_fields(st.phi, st.u)
+            g.force_wide_offsets(wide)
+            out.append(g)
+        return out
+
+    alone, batch, narrow = build(True), build(True), build(False)
+    for n in (9, 8):
+        for g in alone + narrow:
+            g.step(n)
+        L.lbm_batch_step(batch, n)
+    for a, b, c in zip(alone, batch, narrow):
+        assert S.state_digest(a) == S.state_digest(b) == S.state_digest(c)
+    for g in alone + batch + narrow:
+        g.close()
+
+
+# ---------------------------------------------------------------------------
+# the 1024^3 FP16-storage swarm, one step on sampled sub-boxes
+# ---------------------------------------------------------------------------
+
+B = 28          # sub-box edge
+H = 7           # cells next to the sub-box faces that the periodic wrap may reach
+
+
+def film_centres_kdtree(st, count):
+    """Midpoints of the `count` thinnest gaps between sphere surfaces (periodic), from
+    the neighbour pairs within the largest possible gap of interest."""
+    from scipy.spatial import cKDTree
+    n = st.params.nx
+    c = np.array([s.center for s in st.spheres], dtype=float) % n
+    r = np.array([s.radius for s in st.spheres], dtype=float)
+    tree = cKDTree(c, boxsize=n)
+    pairs = np.array(sorted(tree.query_pairs(2 * r.max() + 6.0)))
+    d = c[pairs[:, 1]] - c[pairs[:, 0]]
+    d -= n * np.round(d / n)
+    dist = np.sqrt((d * d).sum(axis=1))
+    gap = dist - r[pairs[:, 0]] - r[pairs[:, 1]]
+    out = []
+    for k in np.argsort(gap)[:count]:
+        i = pairs[k, 0]
+        e = d[k] / dist[k]
+        m = c[i] + e * (r[i] + 0.5 * gap[k])
+        out.append(tuple(int(round(v)) % n for v in m))
+    return out
+
+
+def ulp_half(v):
+    """Spacing of IEEE half-precision numbers at |v| (subnormal spacing 2^-24 below 2^-14)."""
+    a = np.maximum(np.abs(v), 2.0 ** -14)
+    return 2.0 ** (np.floor(np.log2(a)) - 10)
+
+
+def ulp_bf16(v):
+    a = np.maximum(np.abs(v), 2.0 ** -126)
+    return 2.0 ** (np.floor(np.log2(a)) - 7)
+
+
+def check_16bit_step(f_gpu, f_or, ulp, what):
+    """After one step from the same state the GPU's stored population is the FP32
+    result rounded to the 16-bit format: within half a unit in the last place of the
+    format plus the FP32 arithmetic bar.  Returns the share of elements whose
+    rounding differs from rounding the oracle's FP64 result."""
+    scale = np.abs(f_or).max()
+    excess = np.abs(f_gpu - f_or) - 0.5 * ulp(f_or) * (1 + 2.0 ** -10)
+    worst = excess.max() / scale
+    assert worst <= FP32_BAR, (what, worst)
+    return float(np.mean(np.abs(f_gpu - f_or) > 0.5 * ulp(f_or)))
+
+
+@pytest.mark.timeout(900)
+def test_swarm_1024_fp16_one_step_on_sampled_subboxes():
+    announce("full size 1024^3 fp16-storage swarm: generating 20000 bubbles (about 80 s)")
+    st = W.config_swarm(n=1024, bubbles=20000, rmin=6.0, rmax=10.0, gap=2.0, precision="fp16")
+    p = st.params.replace(diag_interval=100)
+    announce("full size 1024^3 fp16-storage swarm (20000 bubbles): sampled sub-boxes")
+    rho_g = 1.0 / p.density_ratio
+    rho_bar = rho_g + (1.0 - rho_g) * float(np.mean(st.phi))
+    rng = np.random.default_rng(23)
+    centres = film_centres_kdtree(st, 4) + [tuple(int(v) for v in rng.integers(0, 1024, 3)) for _ in range(4)]
+    g = L.Lattice(p)
+    g.init_fields(st.phi, None)
+    del st
+    pf, pg = perms(3, 19)
+    ps = p.replace(nx=B, ny=B, nz=B, precision="fp64")
+    inner = (slice(None), slice(H, B - H), slice(H, B - H), slice(H, B - H))
+    g.step(40)
+    chi_films = 0
+    for parity in range(2):
+        before = [g.get_populations(x - B // 2, y - B // 2, z - B // 2, B, B, B) for (x, y, z) in centres]
+        g.step(1)
+        after = [g.get_populations(x - B // 2, y - B // 2, z - B // 2, B, B, B) for (x, y, z) in centres]
+        flips = []
+        for k, ((f0, g0), (f1, g1)) in enumerate(zip(before, after)):
+            o = Oracle(ps)
+            o.set_populations(f0[pf], g0[pg])
+            o.set_rho_mean(rho_bar)
+            if k < 4:
+                chi_films += int(o.nci()[0][inner[1:]].sum())
+            o.step(1)
+            fo, go = o.get_populations()
+            flips.append(check_16bit_step(f1[pf][inner], fo[inner], ulp_half, (parity, centres[k])))
+            eg = np.abs(g1[pg][inner] - go[inner]).max() / np.abs(go[inner]).max()
+            assert eg <= FP32_BAR, (parity, centres[k], eg)
+        print(f"[gpu-case] parity {parity}: share of FP16 roundings off the oracle's {max(flips):.2e}", flush=True)
+    assert chi_films > 0
+    d = g.diagnostics()
+    assert d["finite"] and d["n_droplets"] > 19000
+    g.close()
+
+
+# ---------------------------------------------------------------------------
+# finite-difference phase field: the z march over several chunks
+# ---------------------------------------------------------------------------
+
+def stacked_pair(nz=150, precision="fp64"):
+    """Two droplets near contact stacked along z in a tall box, centres off the
+    lattice symmetry planes."""
+    p = W.Params(dim=3, nx=36, ny=28, nz=nz, width=5.0, sigma=5e-3, a_rep=5e-3, density_ratio=10.0,
+                 precision=precision, cac_solver=1)
+    cx, cy, cz = 17.5 + 0.21, 13.5 + 0.13, (nz - 1) / 2.0 + 0.37
+    A = W.Sphere((cx, cy, cz - 11.0), 9.0)
+    Bs = W.Sphere((cx - 0.17, cy + 0.29, cz + 11.0), 9.0)
+    return W.spheres_state(p, [A, Bs], True, "stacked_pair")
+
+
+@pytest.mark.parametrize("nz", [150, 129])
+def test_muscl_tall_box_fp64(nz):
+    st = stacked_pair(nz)
+    p = st.params
+    announce(f"muscl 36x28x{nz} fp64 100 steps")
+    g = L.Lattice(p)
+    g.init_fields(st.phi, st.u)
+    g.step(100)
+    o = Oracle(p)
+    o.init_fields(st.phi, st.u)
+    o.step(100)
+    errs = errors(g, o)
+    print(f"[gpu-case] errors {errs}", flush=True)
+    assert all(v <= FP64_BAR for v in errs.values()), errs
+    chi_g, part_g, _ = g.nci()
+    chi_o, part_o, _ = o.nci()
+    assert chi_o.sum() > 0 and np.array_equal(chi_g, chi_o) and np.array_equal(part_g, part_o)
+    g.close()
+
+
+def test_muscl_swarm_512_fp32_one_step_on_sampled_subboxes():
+    """The 512^3 FP32 swarm with the finite-difference phase field: one step of each
+    AA parity on sampled sub-boxes, the state being the populations f and phi.
+
+    The near-contact decisions (gate, acceptance tests, partner argmin) are taken in
+    FP32 on the GPU and in FP64 by the oracle.  Where a cell within one cell of the
+    compared region decides differently (a decision flip: its test value lies within
+    rounding of a threshold), the populations it feeds differ by the repulsive flux
+    itself; there the error is only required to stay below 1e-3 of the largest
+    population, and the flip is reported.  Elsewhere the FP32 bar applies."""
+    from tests.test_gpu_fullsize import film_centres
+    st = W.config_swarm(n=512, bubbles=400, precision="fp32")
+    p = st.params.replace(diag_interval=100, cac_solver=1)
+    announce("full size 512^3 fp32 swarm, finite-difference phase field: sampled sub-boxes")
+    g = L.Lattice(p)
+    g.init_fields(st.phi, None)
+    rho_g = 1.0 / p.density_ratio
+    rho_bar = rho_g + (1.0 - rho_g) * float(np.mean(st.phi))
+    rng = np.random.default_rng(29)
+    centres = film_centres(st, 4) + [tuple(int(v) for v in rng.integers(0, 512, 3)) for _ in range(4)]
+    pf, _ = perms(3, 19)
+    ps = p.replace(nx=B, ny=B, nz=B, precision="fp64")
+    inner = (slice(H, B - H),) * 3
+    near = (slice(H - 1, B - H + 1),) * 3
+    g.step(40)
+
+    def sub(a, c):
+        return a[np.ix_(*[(np.arange(B) + c[k] - B // 2) % 512 for k in (2, 1, 0)])]
+
+    chi_films, flipped = 0, 0
+    for parity in range(2):
+        phi0 = g.phi()
+        chi_g, part_g, _ = g.nci()
+        before = [(g.get_populations(x - B // 2, y - B // 2, z - B // 2, B, B, B)[0], sub(phi0, (x, y, z)),
+                   sub(chi_g, (x, y, z)), np.stack([sub(part_g[a], (x, y, z)) for a in range(3)]))
+                  for (x, y, z) in centres]
+        del chi_g, part_g
+        g.step(1)
+        phi1 = g.phi()
+        worst = 0.0
+        for k, (f0, ph0, cg, pg_) in enumerate(before):
+            x, y, z = centres[k]
+            f1 = g.get_populations(x - B // 2, y - B // 2, z - B // 2, B, B, B)[0]
+            o = Oracle(ps)
+            o.set_populations(f0[pf], np.zeros((7, B, B, B)))
+            o.set_phi(ph0)
+            o.set_rho_mean(rho_bar)
+            co, po, _ = o.nci()
+            flips = int(((cg != co) | np.any(pg_ != po, axis=0))[near].sum())
+            if k < 4:
+                chi_films += int(co[inner].sum())
+            o.step(1)
+            fo, _ = o.get_populations()
+            ef = np.abs(f1[pf][(slice(None),) + inner] - fo[(slice(None),) + inner]).max() / np.abs(fo).max()
+            ep = np.abs(sub(phi1, (x, y, z))[inner] - o.phi()[inner]).max()
+            if flips:
+                flipped += 1
+                print(f"[gpu-case] parity {parity} centre {centres[k]}: {flips} near-contact decisions differ "
+                      f"from the oracle's; errors f {ef:.2e} phi {ep:.2e}", flush=True)
+                assert ef <= 1e-3 and ep <= 1e-3, (parity, centres[k], flips, ef, ep)
+            else:
+                worst = max(worst, ef, ep)
+                assert ef <= FP32_BAR and ep <= FP32_BAR, (parity, centres[k], ef, ep)
+        print(f"[gpu-case] muscl parity {parity}: worst relative error without flips {worst:.2e}", flush=True)
+    assert chi_films > 0 and flipped <= 2
+    g.close()
+
+
+# ---------------------------------------------------------------------------
+# served batches against the oracle
+# ---------------------------------------------------------------------------
+
+def three_lattices(dim, precision, a_rep=None):
+    """Three near-contact pairs of different sizes (the centres move with the box)."""
+    nxs = (96, 83, 110) if dim == 2 else (56, 64, 72)
+    return [near_contact_pair(dim, precision, a_rep=a_rep, nx=n) for n in nxs]
+
+
+@pytest.mark.parametrize("dim,precision,steps,bar", [(3, "fp64", 100, FP64_BAR), (2, "fp64", 100, FP64_BAR),
+                                                     (2, "fp32", 1000, FP32_BAR), (3, "fp32", 1000, FP32_BAR)])
+def test_batch_matches_oracle(dim, precision, steps, bar):
+    """Three lattices of different sizes advanced together by lbm_batch_step (one of
+    them one AA step ahead), each against its own oracle run."""
+    states = three_lattices(dim, precision, a_rep=0.02 if dim == 3 and precision == "fp32" else None)
+    announce(f"batch vs oracle {dim}D {precision} steps={steps}")
+    lats = []
+    for k, st in enumerate(states):
+        g = L.Lattice(st.params)
+        g.init_fields(st.phi, st.u)
+        if k == 1:
+            g.step(1)
+        lats.append(g)
+    L.lbm_batch_step(lats, steps - 1)
+    L.lbm_batch_step([lats[0], lats[2]], 1)
+    fields = ("phi", "rho", "u", "pstar") if precision == "fp64" else ("phi", "u")
+    for k, (g, st) in enumerate(zip(lats, states)):
+        assert g.step_count == steps
+        o = Oracle(st.params.replace(precision="fp64"))
+        o.init_fields(st.phi, st.u)
+        o.step(steps)
+        errs = errors(g, o, fields)
+        print(f"[gpu-case] lattice {k} ({st.params.nx} wide): {errs}", flush=True)
+        assert all(v <= bar for v in errs.values()), (k, errs)
+        assert g.diagnostics()["n_droplets"] == o.diagnostics()["n_droplets"]
+    for g in lats:
+        g.close()
+
+
+# ---------------------------------------------------------------------------
+# 16-bit storage through the odd parity's row kernel
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("precision", ["fp16", "bf16"])
+def test_16bit_row_kernel_one_step(precision):
+    """320-wide box: from the same state, one step of each parity (k_collide, then
+    k_collide_row) against the oracle at the storage format's rounding."""
+    st = wide_box(precision)
+    p = st.params
+    announce(f"16-bit row kernel one step {precision}")
+    g = L.Lattice(p)
+    g.init_fields(st.phi, st.u)
+    g.step(40)
+    pf, pg = perms(3, 19)
+    ulp = ulp_half if precision == "fp16" else ulp_bf16
+    for parity in range(2):
+        f0, g0 = g.get_populations()
+        g.step(1)
+        f1, g1 = g.get_populations()
+        o = Oracle(p.replace(precision="fp64"))
+        o.set_populations(f0[pf], g0[pg])
+        o.step(1)
+        fo, go = o.get_populations()
+        share = check_16bit_step(f1[pf], fo, ulp, (precision, parity))
+        eg = rel_linf(g1[pg], go)
+        print(f"[gpu-case] {precision} parity {parity}: share off the oracle's rounding {share:.2e}, g {eg:.2e}",
+              flush=True)
+        assert eg <= FP32_BAR and share < 0.01
+    g.close()
+
+
+@pytest.mark.parametrize("precision", ["fp16", "bf16"])
+def test_16bit_row_kernel_within_rounding_envelope(precision):
+    st = wide_box(precision, a_rep=0.02)
+    steps = 100
+    announce(f"16-bit row kernel {precision} {steps} steps")
+    g = L.Lattice(st.params)
+    g.init_fields(st.phi, st.u)
+    g.step(steps)
+    g.sync()
+    o = Oracle(st.params.replace(precision="fp64"))
+    o.init_fields(st.phi, st.u)
+    o.step(steps)
+    env = roundoff_envelope(st, steps, ("phi", "u"), kind=precision)
+    errs = {f: rel_linf(getattr(g, f)(), getattr(o, f)()) for f in ("phi", "u")}
+    print(f"[gpu-case] {precision} errors {errs} envelope {env}", flush=True)
+    for f in errs:
+        assert errs[f] <= 5 * env[f] + 1e-7, (f, errs[f], env[f])
+    assert g.diagnostics()["n_droplets"] == 2
+    g.close()

@@ -11,7 +11,7 @@ import pytest
 from oracle.oracle import Oracle
 from paper_2603_17481_amd import lbm as L
 from paper_2603_17481_amd import workloads as W
-from tests.helpers import announce, near_contact_pair, rel_linf, roundoff_envelope
+from tests.helpers import announce, near_contact_pair, rel_linf, stored_envelope
 
 pytestmark = pytest.mark.gpu
 
@@ -86,7 +86,7 @@ def test_fp64_collision_2d():
     assert_fields(g, o, FP64_BAR)
     g.step(80)
     o.step(80)
-    env = roundoff_envelope(st, 100, ("phi", "u", "pstar"))
+    env = stored_envelope("collision_2d_muscl_fp64_100")
     print(f"[gpu-case] envelope {env}", flush=True)
     assert_fields(g, o, {f: max(FP64_BAR, 10 * env[f]) for f in env}, fields=("phi", "u", "pstar"))
 
