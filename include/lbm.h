@@ -254,6 +254,21 @@ int lbm_force_wide_offsets(lbm_ctx* ctx, int on);
  * from several host threads at once are not supported. */
 int lbm_batch_step(lbm_ctx* const* ctxs, int count, int n);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the steps of
+ * lbm_batch_step (same kernels, same results bit for bit, same requirements on
+ * the list) with the job table in a fixed device array of the library instead
+ * of an allocation, and no graph.  At most 64 contexts per call; a longer list
+ * returns LBM_E_INVALID.  Each GPU holds one such table (64 KB) until the
+ * process ends, and every call on that GPU rewrites it before its steps read
+ * it, so nothing carries over between calls.  The call is synchronous: it
+ * returns after the steps have run on the first context's stream, so
+ * consecutive calls never share the table; calls from several host threads at
+ * once on one GPU race on it and are not supported.  No memory is allocated
+ * and no graph is created.  Errors as lbm_batch_step, plus LBM_E_HIP if the
+ * table's address cannot be taken. */
+int lbm_batch_step_noalloc(lbm_ctx* const* ctxs, int count, int n);
+
 #ifdef __cplusplus
 }
 #endif

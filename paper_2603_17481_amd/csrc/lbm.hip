@@ -295,6 +295,58 @@ void forget_batches_of(const lbm_ctx* c) {
 }
 
 // ---------------------------------------------------------------------------
+// The job table of lbm_batch_step_noalloc: a fixed device array instead of an
+// allocation.  Host code never passes the array's name to a kernel or a copy:
+// it takes the array's address on each device once, with hipGetSymbolAddress,
+// and uses that pointer.
+// ---------------------------------------------------------------------------
+
+constexpr int STATIC_JOBS = 64;               // most contexts one call may advance
+constexpr size_t STATIC_JOB_BYTES = 1024;     // room per table entry (any precision)
+static __device__ __align__(256) unsigned char scratch[STATIC_JOBS * STATIC_JOB_BYTES];
+
+constexpr int MAX_DEVICES = 64;
+void* g_scratch_ptr[MAX_DEVICES] = {};
+
+// Address of this device's copy of the table, taken once per device with that
+// device current (the caller's current device is restored).
+int scratch_on(int dev, void** out, std::string* why) {
+  if (dev < 0 || dev >= MAX_DEVICES) {
+    *why = "device ordinal beyond the static table's device list";
+    return LBM_E_UNSUPPORTED;
+  }
+  if (!g_scratch_ptr[dev]) {
+    int cur = 0;
+    if (hipGetDevice(&cur) != hipSuccess || (cur != dev && hipSetDevice(dev) != hipSuccess)) {
+      *why = "cannot make the context's device current";
+      return LBM_E_HIP;
+    }
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (cur != dev) (void)hipSetDevice(cur);
+    if (e != hipSuccess || !ptr) {
+      *why = std::string("hipGetSymbolAddress of the static job table: ") + hipGetErrorString(e);
+      return LBM_E_HIP;
+    }
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return LBM_OK;
+}
+
+// Table entries passed by value: K of them per launch, so that the kernel
+// arguments stay within 2 KB.
+template <typename JT, int K>
+struct JobChunk {
+  JT j[K];
+};
+template <typename JT, int K>
+__global__ void k_put_jobs(JT* __restrict__ dst, JobChunk<JT, K> c, int n) {
+  const int t = threadIdx.x;
+  if (t < n) dst[t] = c.j[t];
+}
+
+// ---------------------------------------------------------------------------
 // Typed launch sequences
 // ---------------------------------------------------------------------------
 
@@ -749,6 +801,37 @@ struct Engine {
     jb.nblk = c->L.nblk;
     jb.step = c->step;
     return jb;
+  }
+
+  // The same steps as batch() with the job table in the device's static
+  // array: no allocation, no graph; the table is written on the first context's
+  // stream by small kernels (entries passed by value) and the call waits for
+  // its steps before returning.
+  static int batch_noalloc(lbm_ctx* const* cs, int count, int n, JobT* table) {
+    static_assert(sizeof(JobT) <= STATIC_JOB_BYTES, "job table entry larger than its static slot");
+    constexpr int K = 2048 / sizeof(JobT) > 64 ? 64 : (int)(2048 / sizeof(JobT));
+    static_assert(K >= 1, "job table entry too large for kernel arguments");
+    lbm_ctx* c0 = cs[0];
+    hipStream_t st = c0->stream;
+    for (int i = 1; i < count; ++i) HIP_OR_FAIL(c0, hipStreamSynchronize(cs[i]->stream));
+    int blocks = 0;
+    bool o32 = true;
+    for (int i0 = 0; i0 < count; i0 += K) {
+      JobChunk<JobT, K> chunk{};
+      const int m = std::min(K, count - i0);
+      for (int k = 0; k < m; ++k) {
+        chunk.j[k] = job_entry(cs[i0 + k], blocks);
+        blocks += cs[i0 + k]->L.nblk;
+        o32 = o32 && off32(cs[i0 + k]);
+      }
+      hipLaunchKernelGGL((k_put_jobs<JobT, K>), dim3(1), dim3(64), 0, st, table + i0, chunk, m);
+    }
+    for (int sidx = 0; sidx < n; ++sidx) batch_launch(st, table, count, blocks, sidx, o32);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return c0->fail(LBM_E_HIP, std::string("batch launch: ") + hipGetErrorString(e));
+    HIP_OR_FAIL(c0, hipStreamSynchronize(st));
+    for (int i = 0; i < count; ++i) cs[i]->step += n;
+    return LBM_OK;
   }
 
   static int batch(lbm_ctx* const* cs, int count, int n) {
@@ -1329,6 +1412,26 @@ int lbm_batch_step(lbm_ctx* const* ctxs, int count, int n) {
   const int rc = check_batch(ctxs, count);
   if (rc != LBM_OK) return rc;
   return dispatch(c0, [&](auto E) { return decltype(E)::batch(ctxs, count, n); });
+}
+
+int lbm_batch_step_noalloc(lbm_ctx* const* ctxs, int count, int n) {
+  if (!ctxs || count < 0 || n < 0) return LBM_E_INVALID;
+  if (count == 0 || n == 0) return LBM_OK;
+  lbm_ctx* c0 = ctxs[0];
+  if (!c0) return LBM_E_INVALID;
+  if (count > STATIC_JOBS)
+    return c0->fail(LBM_E_INVALID, "lbm_batch_step_noalloc advances at most " + std::to_string(STATIC_JOBS) +
+                                       " contexts per call (its job table is a fixed device array)");
+  int rc = check_batch(ctxs, count);
+  if (rc != LBM_OK) return rc;
+  void* table = nullptr;
+  std::string why;
+  rc = scratch_on(c0->dev, &table, &why);
+  if (rc != LBM_OK) return c0->fail(rc, why);
+  return dispatch(c0, [&](auto E) {
+    using En = decltype(E);
+    return En::batch_noalloc(ctxs, count, n, (typename En::JobT*)table);
+  });
 }
 
 }  // extern "C"

@@ -107,6 +107,7 @@ def load():
     lib.lbm_save_state.argtypes = [vp, vp, C.c_size_t]
     lib.lbm_load_state.argtypes = [vp, vp, C.c_size_t]
     lib.lbm_batch_step.argtypes = [C.POINTER(vp), C.c_int, C.c_int]
+    lib.lbm_batch_step_noalloc.argtypes = [C.POINTER(vp), C.c_int, C.c_int]
     lib.lbm_timing.argtypes = [vp, C.c_int]
     lib.lbm_kernel_times.argtypes = [vp, dp, C.POINTER(C.c_long)]
     lp = C.POINTER(C.c_long)
@@ -357,3 +358,14 @@ def lbm_batch_step(lattices: Sequence[Lattice], n: int):
     if rc < 0:
         raise LBMError(rc, lib.lbm_last_error(lattices[0].h).decode())
 
+
+def lbm_batch_step_noalloc(lattices: Sequence[Lattice], n: int):
+    """lbm_batch_step without any device allocation (static job table, no graph;
+    synchronous); at most 64 lattices."""
+    if not lattices:
+        return
+    lib = lattices[0].lib
+    arr = (C.c_void_p * len(lattices))(*[lt.h for lt in lattices])
+    rc = lib.lbm_batch_step_noalloc(arr, len(lattices), int(n))
+    if rc < 0:
+        raise LBMError(rc, lib.lbm_last_error(lattices[0].h).decode())
