@@ -93,6 +93,19 @@ typedef struct {
                                 paper's lattice, Sec. 2.1; also the weights of the
                                 isotropic gradient, Laplacian and divergence stencils).
                                 2D: 0 or 9 (D2Q9).                                      */
+  int hydro_store;           /* storage of the hydrodynamic populations: 0 the Q
+                                populations in place (AA pattern); 1 the paper's
+                                "thread-safe" update (Sec. 2.1, Eqs. fneq3, A3rec): each
+                                cell keeps the 13 coefficients of its post-collision
+                                populations (p*, u, F/(2 rho), (1 - omega) A2) in one of
+                                two buffers, and the next step rebuilds each incoming
+                                population from the coefficients of the cell it streams
+                                from.  dim 3, FP64 or FP32, cac_solver 0 only
+                                (LBM_E_UNSUPPORTED otherwise); lbm_set_populations and
+                                lbm_batch_step return LBM_E_UNSUPPORTED.  Initial state:
+                                the coefficients (p*, u, 0, 0), so the first incoming
+                                populations of a cell are the equilibria of the cells
+                                they stream from.                                        */
 } lbm_params;
 
 typedef struct {

@@ -918,6 +918,95 @@ struct PhysT {
 __device__ __forceinline__ float m_rcp(float a) { return __builtin_amdgcn_rcpf(a); }
 __device__ __forceinline__ double m_rcp(double a) { return 1.0 / a; }
 
+// ---------------------------------------------------------------------------
+// Moment storage of the hydrodynamic populations (the paper's "thread-safe"
+// update, Sec. 2.1): instead of its Q post-collision populations a cell keeps
+// the NMOM coefficients they are built from (below), in one of two buffers, and
+// the next step rebuilds each incoming population f_i(x) = f*_i(x - c_i) from the
+// coefficients of the cell it streams from.  Coefficient order:
+//   p*, u (3), h = F / (2 rho) (3), Ah = (1 - omega) A2 (xx yy zz xy xz yz).
+// ---------------------------------------------------------------------------
+constexpr int NMOM = 13;
+
+// f*_i of a cell with coefficients m (c = c_i, w = w_i): the expansion of the
+// collision below, f*_i = w_i [p* - 1.5 tr B + 4.5 c.B.c + 3 c.A1 + t3] with
+// A1 = u + h, B = uu + Ah + u h + h u and
+// t3 = (c.u) (13.5 c.Ah.c + 4.5 ((c.u)^2 - u.u) - 4.5 tr Ah) - 9 c.Ah.u.
+template <typename T>
+__device__ __forceinline__ T post_population(int cx, int cy, int cz, T w, const T m[NMOM]) {
+  const T* u = m + 1;
+  const T* h = m + 4;
+  const T* A = m + 7;
+  const T uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+  const T trA = A[0] + A[1] + A[2];
+  const T uh = u[0] * h[0] + u[1] * h[1] + u[2] * h[2];
+  const T trB = uu + trA + (T)2 * uh;
+  if (cx == 0 && cy == 0 && cz == 0) return w * (m[0] - (T)1.5 * trB);
+  const T cu = sdot(cx, cy, cz, u[0], u[1], u[2]);
+  const T ch = sdot(cx, cy, cz, h[0], h[1], h[2]);
+  const T cAc = ccdot(cx, cy, cz, A);
+  const T Au[3] = {A[0] * u[0] + A[3] * u[1] + A[4] * u[2], A[3] * u[0] + A[1] * u[1] + A[5] * u[2],
+                   A[4] * u[0] + A[5] * u[1] + A[2] * u[2]};
+  const T cAu = sdot(cx, cy, cz, Au[0], Au[1], Au[2]);
+  const T cBc = cu * cu + cAc + (T)2 * cu * ch;
+  const T t3 = cu * ((T)13.5 * cAc + (T)4.5 * (cu * cu - uu) - (T)4.5 * trA) - (T)9 * cAu;
+  return w * (m[0] - (T)1.5 * trB + (T)4.5 * cBc + (T)3 * (cu + ch) + t3);
+}
+
+// Incoming populations of the cell at nb(0, 0, 0) from the coefficients of the
+// cells they stream from (planes of stride S).
+template <int QH, typename T>
+__device__ __forceinline__ void pull_populations(const T* __restrict__ mom, long long S, const Nbr& nb,
+                                                 T fi[HydroQ<QH>::Q]) {
+  using H = HydroQ<QH>;
+#pragma unroll
+  for (int i = 0; i < H::Q; ++i) {
+    const long long j = (long long)nb(-H::cx[i], -H::cy[i], -H::cz[i]);
+    T m[NMOM];
+#pragma unroll
+    for (int k = 0; k < NMOM; ++k) m[k] = mom[k * S + j];
+    fi[i] = post_population(H::cx[i], H::cy[i], H::cz[i], wt<H, T>(i), m);
+  }
+}
+
+// The moments p* = sum f_i, m = sum f_i c_i and M2 = sum f_i c_i c_i (xx yy zz xy
+// xz yz) of the incoming populations, each population rebuilt from the
+// coefficients of the cell it streams from and added at once.  The loads of
+// direction i + 2 are made to wait for the population of direction i (an empty
+// asm statement that takes that population and passes the load offset through),
+// so about two directions' coefficients are in flight; issued all at once, the
+// 13 Q loads held 270 registers and left one wave per SIMD.
+template <int QH, typename T, bool OFF32>
+__device__ __forceinline__ void pull_moments(const T* __restrict__ mom, long long S, const Nbr& nb, T& ps,
+                                             T m[3], T M2[6]) {
+  using H = HydroQ<QH>;
+  ps = (T)0;
+  for (int a = 0; a < 3; ++a) m[a] = (T)0;
+  for (int a = 0; a < 6; ++a) M2[a] = (T)0;
+  unsigned jd[H::Q];
+#pragma unroll
+  for (int i = 0; i < H::Q; ++i) jd[i] = (unsigned)nb(-H::cx[i], -H::cy[i], -H::cz[i]);
+#pragma unroll
+  for (int i = 0; i < H::Q; ++i) {
+    const int cx = H::cx[i], cy = H::cy[i], cz = H::cz[i];
+    T c[NMOM];
+#pragma unroll
+    for (int k = 0; k < NMOM; ++k) c[k] = *plane_at<OFF32>(mom + k * S, jd[i]);
+    const T f = post_population(cx, cy, cz, wt<H, T>(i), c);
+    ps += f;
+    if (cx) m[0] += cx > 0 ? f : -f;
+    if (cy) m[1] += cy > 0 ? f : -f;
+    if (cz) m[2] += cz > 0 ? f : -f;
+    if (cx) M2[0] += f;
+    if (cy) M2[1] += f;
+    if (cz) M2[2] += f;
+    if (cx && cy) M2[3] += cx * cy > 0 ? f : -f;
+    if (cx && cz) M2[4] += cx * cz > 0 ? f : -f;
+    if (cy && cz) M2[5] += cy * cz > 0 ? f : -f;
+    if (i + 2 < H::Q) asm volatile("" : "+v"(jd[i + 2]) : "v"(f));
+  }
+}
+
 // Post-collision populations, written as Hermite coefficients.  f^eq, the
 // regularised non-equilibrium part and S/2 all lie in the span of the Hermite
 // polynomials up to third order (the Guo term has no third-order part), so
@@ -932,7 +1021,7 @@ __device__ __forceinline__ double m_rcp(double a) { return 1.0 / a; }
 // contributions to the FP64 diagnostics; MODE_DRY leaves the populations and
 // writes p*, rho, u, F to macro (when given).
 template <int DIM, int QH, int PAR, int MODE, typename T, typename FS, typename GS, bool OFF32,
-          bool XCH = false, bool PRE = false>
+          bool XCH = false, bool PRE = false, bool MOM = false>
 __device__ __forceinline__ void collide_cell(const Planes<FS, GS>& pl, const T* __restrict__ phi,
                                              const T* __restrict__ J,
                                              const unsigned* __restrict__ flags, const Geo& geo,
@@ -940,12 +1029,17 @@ __device__ __forceinline__ void collide_cell(const Planes<FS, GS>& pl, const T* 
                                              T* __restrict__ uout, int x, int y, int z,
                                              double acc[NPART], FS* xf = nullptr,
                                              GS* xg = nullptr, const T* fpre = nullptr,
-                                             const T* gpre = nullptr) {
+                                             const T* gpre = nullptr, const T* __restrict__ min = nullptr,
+                                             T* __restrict__ mout = nullptr) {
   using H = HydroQ<QH>;
   using P = Phase<DIM>;
   using TL = NciTile<DIM, T>;
   constexpr int Q = H::Q, QG = P::Q;
   static_assert(!XCH || PAR == 1, "the row exchange serves the odd parity");
+  static_assert(!MOM || (!XCH && !PRE && DIM == 3), "moment storage: 3D, cell-wise kernel");
+  // MOM: the hydrodynamic populations are rebuilt from the coefficients in min
+  // (moment storage, see post_population) and the new coefficients go to mout;
+  // the phase-field populations keep the AA pattern of parity PAR.
   const Nbr nb(x, y, z, geo);
   const unsigned idx = (unsigned)nb(0, 0, 0);
   // XCH (k_collide_row): the odd parity's x-shifted populations of this cell's
@@ -985,7 +1079,7 @@ __device__ __forceinline__ void collide_cell(const Planes<FS, GS>& pl, const T* 
   // that the two kinds are not merged) where it is shifted along x
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
-    if (PAR == 1 && H::cx[i] != 0) continue;
+    if (MOM || (PAR == 1 && H::cx[i] != 0)) continue;
     if constexpr (PRE)
       fi[i] = fpre[i];
     else
@@ -1001,16 +1095,20 @@ __device__ __forceinline__ void collide_cell(const Planes<FS, GS>& pl, const T* 
       fi[i] = Store<FS>::ld(xf + (2 * j + 1) * geo.nx + xm, pp.fref[i]);
       fi[i + 1] = Store<FS>::ld(xf + 2 * j * geo.nx + xp, pp.fref[i]);
     }
-  } else {
+  } else if constexpr (!MOM) {
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
       if (PAR == 0 || H::cx[i] == 0) continue;
       fi[i] = Store<FS>::ld(pf.template at<OFF32>(opp(i), -H::cx[i], -H::cy[i], -H::cz[i]), pp.fref[i]);
     }
   }
-  T ps = fi[0], m[3] = {0, 0, 0}, M2[6] = {0, 0, 0, 0, 0, 0};  // xx yy zz xy xz yz
+  T ps, m[3] = {0, 0, 0}, M2[6] = {0, 0, 0, 0, 0, 0};  // xx yy zz xy xz yz
+  if constexpr (MOM)
+    pull_moments<QH, T, OFF32>(min, S, nb, ps, m, M2);
+  else
+    ps = fi[0];
 #pragma unroll
-  for (int i = 1; i < Q; i += 2) {
+  for (int i = 1; i < (MOM ? 0 : Q); i += 2) {
     const T s = fi[i] + fi[i + 1], d = fi[i] - fi[i + 1];
     ps += s;
     const int cx = H::cx[i], cy = H::cy[i], cz = H::cz[i];
@@ -1088,6 +1186,17 @@ __device__ __forceinline__ void collide_cell(const Planes<FS, GS>& pl, const T* 
     const T A1[3] = {u[0] + F[0] * inv2rho, u[1] + F[1] * inv2rho, u[2] + F[2] * inv2rho};
     const T base = ps - (T)1.5 * trB;
     const T k3 = (T)13.5 * om1, k3t = (T)4.5 * om1 * trA, k3u = (T)9 * om1;
+    if constexpr (MOM) {
+      // the coefficients of f* (post_population rebuilds it where it streams to)
+      st_nt(mout + idx, ps);
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        st_nt(mout + (1 + a) * S + idx, u[a]);
+        st_nt(mout + (4 + a) * S + idx, F[a] * inv2rho);
+      }
+#pragma unroll
+      for (int k = 0; k < 6; ++k) st_nt(mout + (7 + k) * S + idx, om1 * A[k]);
+    } else {
     Store<FS>::sth(pf.template at<OFF32>(0, 0, 0, 0), wt<H, T>(0) * base, pp.fref[0]);
     T fsx[Q];   // odd parity, c_x != 0: stored plain after the loop
 #pragma unroll
@@ -1128,6 +1237,7 @@ __device__ __forceinline__ void collide_cell(const Planes<FS, GS>& pl, const T* 
           Store<FS>::st(pf.template at<OFF32>(i + 1, -cx, -cy, -cz), fsx[i + 1], pp.fref[i]);
         }
       }
+    }
     }
     if (uout) {
       // finite-difference phase field: the velocity of this collision and the
@@ -1270,6 +1380,29 @@ __global__ __launch_bounds__(NT) void k_collide(Planes<FS, GS> pl, const T* __re
   if (valid)
     collide_cell<DIM, QH, PAR, MODE, T, FS, GS, OFF32>(pl, phi, J, flags, geo, pp, nci_on, macro, uout, x, y, z,
                                                        acc);
+  if constexpr (MODE != MODE_STEP) block_partials(acc, partials);
+}
+
+// Fused collide + stream with the hydrodynamic populations in moment storage
+// (3D): reads the coefficients of min, writes those of mout; the phase-field
+// populations stay in AA parity PAR.
+template <int QH, int PAR, int MODE, typename T, bool OFF32>
+__global__ __launch_bounds__(NT) void k_collide_mom(Planes<T, T> pl, const T* __restrict__ min,
+                                                    T* __restrict__ mout, const T* __restrict__ phi,
+                                                    const T* __restrict__ J, const unsigned* __restrict__ flags,
+                                                    unsigned* __restrict__ cnt_other, Geo geo, PhysT<T> pp,
+                                                    int nci_on, T* __restrict__ macro,
+                                                    double* __restrict__ partials) {
+  if (nci_on && blockIdx.x == 0 && threadIdx.x == 0) *cnt_other = 0u;
+  int x, y, z;
+  block_cell(slab_block(geo), geo, x, y, z);
+  const bool valid = x < geo.nx && y < geo.ny;
+  double acc[NPART] = {};
+  if (MODE == MODE_STEP && !valid) return;
+  if (valid)
+    collide_cell<3, QH, PAR, MODE, T, T, T, OFF32, false, false, true>(
+        pl, phi, J, flags, geo, pp, nci_on, macro, nullptr, x, y, z, acc, nullptr, nullptr, nullptr, nullptr, min,
+        mout);
   if constexpr (MODE != MODE_STEP) block_partials(acc, partials);
 }
 
@@ -1881,6 +2014,69 @@ __global__ __launch_bounds__(NT) void k_init(FS* __restrict__ f, GS* __restrict_
   for (int k = 0; k < P::Q; ++k) {
     const T cj = k == 0 ? (T)0 : sdot(P::cx[k], P::cy[k], P::cz[k], jv[0], jv[1], jv[2]);
     g[pop_elem(k, x, y, z, geo, P::Q)] = (GS)(wt<P, T>(k) * (ph + cj * (T)P::inv_cs2));
+  }
+}
+
+// Moment storage, initial state: the coefficients (p*, u, 0, 0), whose
+// populations are feq(p*, u) (Eq. feq3), so that the first incoming populations
+// of a cell are the equilibria of the cells they stream from; g = geq(phi, u, n)
+// in natural layout (parity 0).
+template <int QH, typename T>
+__global__ __launch_bounds__(NT) void k_init_mom(T* __restrict__ mom, T* __restrict__ g,
+                                                 const T* __restrict__ phi, const T* __restrict__ uin,
+                                                 const T* __restrict__ psin, Geo geo, PhysT<T> pp) {
+  using H = HydroQ<QH>;
+  using P = Phase<3>;
+  int x, y, z;
+  block_cell(swizzled_block(), geo, x, y, z);
+  if (x >= geo.nx || y >= geo.ny) return;
+  const Nbr nb(x, y, z, geo);
+  const int idx = nb(0, 0, 0);
+  const long long S = geo.S;
+  const T u[3] = {uin[idx], uin[S + idx], uin[2 * S + idx]};
+  mom[idx] = psin[idx];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    mom[(1 + a) * S + idx] = u[a];
+    mom[(4 + a) * S + idx] = (T)0;
+  }
+#pragma unroll
+  for (int k = 0; k < 6; ++k) mom[(7 + k) * S + idx] = (T)0;
+  T gr[3], lap;
+  grad_lap<QH, T>([&](int i) { return phi[nb(H::cx[i], H::cy[i], H::cz[i])]; }, gr, lap);
+  const T ph = phi[idx];
+  T gmag = m_sqrt(gr[0] * gr[0] + gr[1] * gr[1] + gr[2] * gr[2]);
+  const T kc = pp.kc * ph * ((T)1 - ph) / (gmag + pp.eps_n);
+  const T jv[3] = {ph * u[0] + kc * gr[0], ph * u[1] + kc * gr[1], ph * u[2] + kc * gr[2]};
+#pragma unroll
+  for (int k = 0; k < P::Q; ++k) {
+    const T cj = k == 0 ? (T)0 : sdot(P::cx[k], P::cy[k], P::cz[k], jv[0], jv[1], jv[2]);
+    g[pop_elem(k, x, y, z, geo, P::Q)] = (T)(wt<P, T>(k) * (ph + cj * (T)P::inv_cs2));
+  }
+}
+
+// Moment storage: incoming populations on a wrapped box, rebuilt from the
+// coefficients, as doubles, SoA [q][box]; g as k_getpop.
+template <int QH, int PAR, typename T>
+__global__ __launch_bounds__(NT) void k_getpop_mom(const T* __restrict__ mom, const T* __restrict__ g, Geo geo,
+                                                   int x0, int y0, int z0, int bxn, int byn, int bzn,
+                                                   double* __restrict__ fo, double* __restrict__ go) {
+  using H = HydroQ<QH>;
+  using P = Phase<3>;
+  const long long B = (long long)bxn * byn * bzn;
+  const long long e = (long long)blockIdx.x * NT + threadIdx.x;
+  if (e >= B) return;
+  const int lx = (int)(e % bxn), ly = (int)((e / bxn) % byn), lz = (int)(e / ((long long)bxn * byn));
+  const int x = wrapi(x0 + lx, geo.nx), y = wrapi(y0 + ly, geo.ny), z = wrapi(z0 + lz, geo.nz);
+  const Nbr nb(x, y, z, geo);
+  T fi[H::Q];
+  pull_populations<QH, T>(mom, geo.S, nb, fi);
+  for (int i = 0; i < H::Q; ++i) fo[i * B + e] = (double)fi[i];
+  const PopNbr<const T> pg(g, x, y, z, geo, P::Q);
+  for (int k = 0; k < P::Q; ++k) {
+    const T* src = PAR == 0 ? pg.template at<false>(k, 0, 0, 0)
+                            : pg.template at<false>(opp(k), -P::cx[k], -P::cy[k], -P::cz[k]);
+    go[k * B + e] = (double)*src;
   }
 }
 

@@ -13,6 +13,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/lbm.h"
@@ -89,6 +90,18 @@ bool valid_params(const lbm_params* p, std::string* why) {
   if (p->dispersed < -1 || p->dispersed > 1) return bad("dispersed must be -1, 0 or 1");
   if (p->diag_interval < 0) return bad("diag_interval must be >= 0");
   if (p->cac_solver != 0 && p->cac_solver != 1) return bad("cac_solver must be 0 or 1");
+  if (p->hydro_store != 0 && p->hydro_store != 1) return bad("hydro_store must be 0 or 1");
+  return true;
+}
+
+// Combinations that are valid but not built: moment storage runs in 3D, with
+// FP64 or FP32 coefficients and the lattice Boltzmann phase field.
+bool supported(const lbm_params* p, std::string* why) {
+  if (p->hydro_store == 1 && (p->dim != 3 || (p->precision != LBM_FP64 && p->precision != LBM_FP32) ||
+                              p->cac_solver != 0)) {
+    *why = "moment storage (hydro_store 1) needs dim 3, FP64 or FP32, and cac_solver 0";
+    return false;
+  }
   return true;
 }
 
@@ -132,7 +145,10 @@ Layout make_layout(const lbm_params* p) {
   L.ntiles = L.ntx * L.nty * L.ntz;
   const size_t rs = real_size(p->precision), fs = fstore_size(p->precision);
   size_t o = 0;
-  L.off_f = o;   o = align256(o + (size_t)q_hydro(p) * L.N * fs);
+  // populations f (AA, one copy), or with moment storage two buffers of NMOM
+  // coefficient planes
+  L.off_f = o;
+  o = align256(o + (p->hydro_store ? 2 * (size_t)NMOM * L.S * rs : (size_t)q_hydro(p) * L.N * fs));
   L.off_g = o;   o = align256(o + (size_t)q_phase(p->dim) * L.N * rs);
   L.off_phi = o; o = align256(o + (size_t)L.S * rs);
   L.off_J = o;   o = align256(o + (size_t)p->dim * L.S * rs);
@@ -180,6 +196,7 @@ struct lbm_ctx {
   long k_cnt[5] = {0, 0, 0, 0, 0};
   int phi_cur = 0;   // finite-difference phase field: which phi buffer holds the state
   bool wide_offsets = false;   // lbm_force_wide_offsets: 64-bit offset kernels at any size
+  int mom_cur = 0;   // moment storage: which coefficient buffer holds the state
 
   void* f() const { return ws + L.off_f; }
   void* g() const { return ws + L.off_g; }
@@ -187,6 +204,9 @@ struct lbm_ctx {
   void* phi_next() const { return ws + (phi_cur ? L.off_phi : L.off_phi2); }
   void* ua() const { return ws + L.off_ua; }
   bool fd() const { return p.cac_solver != 0; }
+  bool mom() const { return p.hydro_store != 0; }
+  // coefficient buffer k of the moment storage (NMOM planes of stride S)
+  void* mom_buf(int k) const { return ws + L.off_f + (size_t)k * NMOM * L.S * real_size(p.precision); }
   void* J() const { return ws + L.off_J; }
   unsigned* flags(int k) const { return (unsigned*)(ws + L.off_flags) + (size_t)k * L.ntiles; }
   unsigned* list(int k) const { return (unsigned*)(ws + L.off_list) + (size_t)k * L.ntiles; }
@@ -465,6 +485,21 @@ struct Engine {
 
   template <int MODE>
   static void collide_pass(lbm_ctx* c, int par, T* macro) {
+    if constexpr (DIM == 3 && std::is_same<FS, T>::value && std::is_same<GS, T>::value) {
+      if (c->mom()) {
+        const bool o32 = off32(c);
+        auto k = par == 0 ? (o32 ? k_collide_mom<QH, 0, MODE, T, true> : k_collide_mom<QH, 0, MODE, T, false>)
+                          : (o32 ? k_collide_mom<QH, 1, MODE, T, true> : k_collide_mom<QH, 1, MODE, T, false>);
+        Planes<T, T> pl{nullptr, (T*)c->g()};
+        Timed tm(c, 2);
+        hipLaunchKernelGGL(k, rows(c), dim3(NT), 0, c->stream, pl, (const T*)c->mom_buf(c->mom_cur),
+                           (T*)c->mom_buf(1 - c->mom_cur), (const T*)c->phi(), (const T*)c->J(),
+                           (const unsigned*)c->flags(par), c->cnt() + (1 - par), c->geo, physT(c),
+                           c->nci_on() ? 1 : 0, macro, c->pa());
+        if (MODE != MODE_DRY) c->mom_cur ^= 1;
+        return;
+      }
+    }
     const bool o32 = off32(c);
     if constexpr (DIM == 3 && MODE == MODE_STEP) {
       if (par == 1 && row_collide(c)) {
@@ -590,8 +625,18 @@ struct Engine {
         rc = c->fail(LBM_E_HIP, "host to device copy failed");
         break;
       }
-      hipLaunchKernelGGL((k_init<DIM, QH, T, FS, GS>), rows(c), dim3(NT), 0, c->stream, (FS*)c->f(),
-                         (GS*)c->g(), (const T*)c->phi(), (const T*)du, (const T*)dps, c->geo, physT(c));
+      bool done = false;
+      if constexpr (DIM == 3 && std::is_same<FS, T>::value && std::is_same<GS, T>::value) {
+        if (c->mom()) {
+          c->mom_cur = 0;
+          hipLaunchKernelGGL((k_init_mom<QH, T>), rows(c), dim3(NT), 0, c->stream, (T*)c->mom_buf(0),
+                             (T*)c->g(), (const T*)c->phi(), (const T*)du, (const T*)dps, c->geo, physT(c));
+          done = true;
+        }
+      }
+      if (!done)
+        hipLaunchKernelGGL((k_init<DIM, QH, T, FS, GS>), rows(c), dim3(NT), 0, c->stream, (FS*)c->f(),
+                           (GS*)c->g(), (const T*)c->phi(), (const T*)du, (const T*)dps, c->geo, physT(c));
       if (hipGetLastError() != hipSuccess || hipStreamSynchronize(c->stream) != hipSuccess)
         rc = c->fail(LBM_E_HIP, "initialisation kernel failed");
     } while (0);
@@ -610,10 +655,22 @@ struct Engine {
       return c->fail(LBM_E_OOM, "temporary allocation failed");
     }
     const int par = (int)(c->step & 1);
-    auto k = par == 0 ? k_getpop<DIM, QH, 0, T, FS, GS> : k_getpop<DIM, QH, 1, T, FS, GS>;
-    hipLaunchKernelGGL(k, dim3((unsigned)((B + NT - 1) / NT)), dim3(NT), 0, c->stream,
-                       (const FS*)c->f(), (const GS*)c->g(), c->geo, physT(c), x0, y0, z0, bx, by, bz,
-                       df, dg);
+    bool done = false;
+    if constexpr (DIM == 3 && std::is_same<FS, T>::value && std::is_same<GS, T>::value) {
+      if (c->mom()) {
+        auto k = par == 0 ? k_getpop_mom<QH, 0, T> : k_getpop_mom<QH, 1, T>;
+        hipLaunchKernelGGL(k, dim3((unsigned)((B + NT - 1) / NT)), dim3(NT), 0, c->stream,
+                           (const T*)c->mom_buf(c->mom_cur), (const T*)c->g(), c->geo, x0, y0, z0, bx, by, bz,
+                           df, dg);
+        done = true;
+      }
+    }
+    if (!done) {
+      auto k = par == 0 ? k_getpop<DIM, QH, 0, T, FS, GS> : k_getpop<DIM, QH, 1, T, FS, GS>;
+      hipLaunchKernelGGL(k, dim3((unsigned)((B + NT - 1) / NT)), dim3(NT), 0, c->stream,
+                         (const FS*)c->f(), (const GS*)c->g(), c->geo, physT(c), x0, y0, z0, bx, by, bz,
+                         df, dg);
+    }
     int rc = LBM_OK;
     if (hipStreamSynchronize(c->stream) != hipSuccess ||
         (fo && hipMemcpy(fo, df, sizeof(double) * HydroQ<QH>::Q * B, hipMemcpyDeviceToHost)) ||
@@ -1014,6 +1071,10 @@ int lbm_create(const lbm_params* p, void* dev_workspace, size_t ws_bytes, void* 
     g_create_error = "hipGetDeviceProperties failed";
     return LBM_E_HIP;
   }
+  if (!supported(p, &why)) {
+    g_create_error = why;
+    return LBM_E_UNSUPPORTED;
+  }
   if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) {
     g_create_error = std::string("this library is built for gfx950, device is ") + prop.gcnArchName;
     return LBM_E_UNSUPPORTED;
@@ -1252,6 +1313,9 @@ int lbm_set_populations(lbm_ctx* c, const double* f, const double* g) {
   if (!f || !g) return c->fail(LBM_E_INVALID, "null populations");
   if (c->fd())
     return c->fail(LBM_E_UNSUPPORTED, "the finite-difference phase field has no populations g to set");
+  if (c->mom())
+    return c->fail(LBM_E_UNSUPPORTED,
+                   "moment storage keeps post-collision coefficients, which arbitrary populations need not have");
   // mean phi (for the buoyancy reference) from the phase-field populations
   const long long N = c->L.N;
   const int qg = q_phase(c->p.dim);
@@ -1283,13 +1347,14 @@ struct StateHeader {
   long long step;
   double rho_mean;
   long long dispersed;
-  long long dim, nx, ny, nz, precision, hydro_q, cac_solver;
+  long long dim, nx, ny, nz, precision, hydro_q, cac_solver, hydro_store, store_cur;
 };
 constexpr unsigned long long STATE_MAGIC = 0x4c424d5354415445ULL;  // "LBMSTATE"
-constexpr long long STATE_VERSION = 2;
+constexpr long long STATE_VERSION = 3;
 StateHeader state_header(const lbm_ctx* c) {
   return StateHeader{STATE_MAGIC, STATE_VERSION, c->step, c->phys.rho_mean, c->dispersed, c->p.dim,
-                     c->p.nx, c->p.ny, c->p.nz, c->p.precision, q_hydro(&c->p), c->p.cac_solver};
+                     c->p.nx, c->p.ny, c->p.nz, c->p.precision, q_hydro(&c->p), c->p.cac_solver,
+                     c->p.hydro_store, c->mom_cur};
 }
 size_t pop_bytes(const lbm_ctx* c) {
   return c->L.off_phi;  // f and g are the first two regions of the workspace
@@ -1327,7 +1392,8 @@ int lbm_load_state(lbm_ctx* c, const void* buf, size_t bytes) {
   if (h.magic != STATE_MAGIC || h.version != STATE_VERSION)
     return c->fail(LBM_E_INVALID, "not a state of this library version");
   if (h.dim != want.dim || h.nx != want.nx || h.ny != want.ny || h.nz != want.nz ||
-      h.precision != want.precision || h.hydro_q != want.hydro_q || h.cac_solver != want.cac_solver)
+      h.precision != want.precision || h.hydro_q != want.hydro_q || h.cac_solver != want.cac_solver ||
+      h.hydro_store != want.hydro_store)
     return c->fail(LBM_E_INVALID, "state does not match this context (box, precision, lattice or solver)");
   HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
   HIP_OR_FAIL(c, hipMemcpy(c->ws, (const char*)buf + sizeof(h), pop_bytes(c), hipMemcpyHostToDevice));
@@ -1336,6 +1402,7 @@ int lbm_load_state(lbm_ctx* c, const void* buf, size_t bytes) {
     HIP_OR_FAIL(c, hipMemcpy(c->phi(), (const char*)buf + sizeof(h) + pop_bytes(c), phi_state_bytes(c),
                              hipMemcpyHostToDevice));
   c->step = h.step;
+  c->mom_cur = (int)h.store_cur;
   c->dispersed = (int)h.dispersed;
   c->phys.rho_mean = h.rho_mean;
   reset_nci_state(c);
@@ -1392,6 +1459,8 @@ int check_batch(lbm_ctx* const* ctxs, int count) {
     if (!c->initialised) return c0->fail(LBM_E_STATE, "batch holds an uninitialised context");
     if (c->fd())
       return c0->fail(LBM_E_UNSUPPORTED, "batches step the lattice Boltzmann phase field only (cac_solver 0)");
+    if (c->mom())
+      return c0->fail(LBM_E_UNSUPPORTED, "batches step the AA population storage only (hydro_store 0)");
     if (c->dev != c0->dev || c->p.dim != c0->p.dim || c->p.precision != c0->p.precision ||
         q_hydro(&c->p) != q_hydro(&c0->p))
       return c0->fail(LBM_E_INVALID, "batch contexts must share device, lattice and precision");

@@ -45,7 +45,7 @@ class lbm_params(C.Structure):
         ("eps_n", C.c_double), ("eps_q", C.c_double), ("tie_eps", C.c_double),
         ("rep_orient", C.c_int), ("dispersed", C.c_int), ("cac_compress", C.c_int),
         ("diag_interval", C.c_int), ("pstar_ref", C.c_double), ("cac_solver", C.c_int),
-        ("hydro_q", C.c_int),
+        ("hydro_q", C.c_int), ("hydro_store", C.c_int),
     ]
 
 
@@ -145,6 +145,7 @@ def to_c_params(p: Params) -> lbm_params:
     hq = getattr(p, "hydro_q", 19)
     # 2D is always D2Q9: the 3D default passes as 0, anything else is refused by the library
     s.hydro_q = hq if p.dim == 3 or hq not in (9, 19) else 0
+    s.hydro_store = getattr(p, "hydro_store", 0)
     return s
 
 

@@ -59,6 +59,7 @@ class Params:
     cac_compress: int = 1        # 0 switches the counter-gradient flux off (diffusion test)
     cac_solver: int = 0          # phase field: 0 lattice Boltzmann (g), 1 finite-difference MUSCL-TVD
     hydro_q: int = 19            # 3D hydrodynamic lattice: D3Q19 or D3Q27 (2D is always D2Q9)
+    hydro_store: int = 0         # 3D: 0 populations in place (AA), 1 post-collision moments
     diag_interval: int = 0       # periodic on-device diagnostics every K steps (0: never)
     pstar_ref: float = 0.0       # reference p* of the 16-bit population encoding
 

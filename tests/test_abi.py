@@ -41,12 +41,17 @@ def test_workspace_bytes_model():
     assert 4 * n * (1 + 6) <= bfd - b < 4 * n * (1 + 6) * 1.02
     # D3Q27 stores 8 more hydrodynamic populations
     assert L.lbm_workspace_bytes(p.replace(hydro_q=27)) - b == 4 * n * 8
+    # moment storage: two buffers of 13 coefficient planes instead of 19 (or 27) populations
+    for hq, q in ((19, 19), (27, 27)):
+        bm = L.lbm_workspace_bytes(p.replace(hydro_q=hq, hydro_store=1))
+        ba = L.lbm_workspace_bytes(p.replace(hydro_q=hq))
+        assert abs((bm - ba) - 4 * n * (2 * 13 - q)) < 4 * 13 * 2 * 2048
 
 
 @pytest.mark.parametrize("bad", [dict(dim=4), dict(nx=0), dict(tau=0.5), dict(nci_window=5),
                                  dict(eps_q=0.2), dict(rep_orient=2), dict(precision="fp8"),
                                  dict(cac_solver=2), dict(dim=3, nz=8, hydro_q=15),
-                                 dict(hydro_q=27)])
+                                 dict(hydro_q=27), dict(hydro_store=2)])
 def test_invalid_params_rejected(bad):
     kw = dict(dim=2, nx=32, ny=32, nz=1)
     kw.update(bad)
