@@ -40,7 +40,7 @@ METRIC = "MLUPS + % of HBM roofline per coupled step; served jobs/s + p99 latenc
 KERNEL_SRC = os.path.join(ROOT, "paper_2603_17481_amd", "csrc", "kernels.hpp")
 COUNTERS = [os.path.join(ROOT, "profiles", f) for f in
             ("collide_swarm512_fp32_counters.md", "kernels_swarm512_fp32_muscl.md",
-             "kernels_swarm512_fp32_d3q27.md")]
+             "kernels_swarm512_fp32_d3q27.md", "kernels_swarm1024_fp16.md")]
 
 # Algorithmic bytes per cell (each population read once and written once, phi
 # read once; J read only in near-contact tiles, added per tile cell).
