@@ -1671,16 +1671,11 @@ __global__ __launch_bounds__(NT) void k_muscl(const T* __restrict__ phi, T* __re
 // or registers (about ten global loads per cell instead of about seventy), and
 // the loads of the next plane are issued before the update of this one, so
 // that their latency hides behind its arithmetic.
-#ifndef MUSCL_ZRUN
-#define MUSCL_ZRUN 64
-#endif
-#ifndef MUSCL_TY32
-#define MUSCL_TY32 4
-#endif
-constexpr int MZ_TX = 64;
+constexpr int MUSCL_ZRUN = 64;   // planes a block marches through
+constexpr int MZ_TX = 64;        // cells per block row
 template <typename T>
 struct MuslTile {
-  static constexpr int TY = sizeof(T) == 8 ? 4 : MUSCL_TY32;   // rows per block
+  static constexpr int TY = 4;   // rows per block (8 and 16 were slower: 1.16, 1.17 against 1.14 ms)
   static constexpr int NT = MZ_TX * TY;
   static constexpr int PW = MZ_TX + 4, PN = PW * (TY + 4);   // phi planes, halo 2
   static constexpr int AW = MZ_TX + 2, AN = AW * (TY + 2);   // a and u planes, halo 1
@@ -2146,8 +2141,16 @@ struct Job {
   int nci_on;
   T q_th;
   int blk0, nblk;     // first block of this lattice in the batch grid, and its block count
+  int pblk0, pnblk;   // the same in the grid of the phi pass, whose blocks take PHI_PER row blocks each
   long long step;     // completed steps of this lattice when the launch sequence starts
 };
+
+// Row blocks per block of the multi-lattice phi pass: its per-cell work is a few
+// loads, so each block amortises its job-table lookup over several row blocks.
+constexpr int PHI_PER = 4;
+// Lattices of a batch whose near-contact work is spread as one list (more fall
+// back to a loop over the lattices).
+constexpr int NCI_FLAT_JOBS = 64;
 
 template <typename JT>
 __device__ __forceinline__ int find_job(const JT* __restrict__ jobs, int njobs, int t) {
@@ -2160,29 +2163,127 @@ __device__ __forceinline__ int find_job(const JT* __restrict__ jobs, int njobs, 
   return lo;
 }
 
+template <typename JT>
+__device__ __forceinline__ int find_job_phi(const JT* __restrict__ jobs, int njobs, int t) {
+  int lo = 0, hi = njobs - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (jobs[mid].pblk0 <= t) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
 template <int DIM, typename T, typename FS, typename GS>
 __global__ __launch_bounds__(NT) void k_phi_multi(const Job<T, FS, GS>* __restrict__ jobs, int njobs,
                                                   int s) {
   const int t = swizzled_block();
-  const Job<T, FS, GS>& jb = jobs[find_job(jobs, njobs, t)];
-  const int lb = t - jb.blk0;
+  const Job<T, FS, GS>& jb = jobs[find_job_phi(jobs, njobs, t)];
   const int par = (int)((jb.step + s) & 1);
-  if (jb.nci_on && lb == 0 && threadIdx.x == 0) jb.cnt[2] = 0u;
-  int x, y, z;
-  block_cell(lb, jb.geo, x, y, z);
-  if (x >= jb.geo.nx || y >= jb.geo.ny) return;
-  if (par == 0)
-    phi_cell<DIM, 0, T, GS>(jb.pl.g, jb.phi, jb.geo, jb.flags[0], jb.list[0], jb.cnt, jb.nci_on,
-                            jb.q_th, x, y, z);
-  else
-    phi_cell<DIM, 1, T, GS>(jb.pl.g, jb.phi, jb.geo, jb.flags[1], jb.list[1], jb.cnt + 1,
-                            jb.nci_on, jb.q_th, x, y, z);
+  if (jb.nci_on && t == jb.pblk0 && threadIdx.x == 0) jb.cnt[2] = 0u;
+#pragma unroll
+  for (int r = 0; r < PHI_PER; ++r) {
+    const int lb = (t - jb.pblk0) * PHI_PER + r;
+    if (lb >= jb.nblk) break;
+    int x, y, z;
+    block_cell(lb, jb.geo, x, y, z);
+    if (x >= jb.geo.nx || y >= jb.geo.ny) continue;
+    if (par == 0)
+      phi_cell<DIM, 0, T, GS>(jb.pl.g, jb.phi, jb.geo, jb.flags[0], jb.list[0], jb.cnt, jb.nci_on,
+                              jb.q_th, x, y, z);
+    else
+      phi_cell<DIM, 1, T, GS>(jb.pl.g, jb.phi, jb.geo, jb.flags[1], jb.list[1], jb.cnt + 1,
+                              jb.nci_on, jb.q_th, x, y, z);
+  }
 }
 
+// Near-contact pass of a batch.  Up to NCI_FLAT_JOBS lattices: the listed tiles
+// of all lattices form one list (prefix sums over the lattices' tile counts), so
+// that the blocks share the work whatever its split between lattices, and each
+// block reads the job table once per tile instead of looping over every
+// lattice.  A tile's phi halo is prefetched during the previous tile, also
+// across lattices.  More lattices: a loop over them, each spread over all blocks.
 template <int DIM, int QH, typename T, typename FS, typename GS>
 __global__ __launch_bounds__(NT_NCI) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 1))) void k_nci_multi(const Job<T, FS, GS>* __restrict__ jobs,
                                                       int njobs, int s) {
   __shared__ NciShared<DIM, T> sm;
+  __shared__ unsigned pre[NCI_FLAT_JOBS + 1], preo[NCI_FLAT_JOBS + 1];
+  if (njobs <= NCI_FLAT_JOBS) {
+    if (threadIdx.x < 64) {
+      const int j = (int)threadIdx.x;
+      unsigned a = 0u, b = 0u;
+      if (j < njobs && jobs[j].nci_on) {
+        const int par = (int)((jobs[j].step + s) & 1);
+        a = jobs[j].cnt[par];
+        b = jobs[j].cnt[1 - par];
+      }
+      // inclusive scan over the wave
+#pragma unroll
+      for (int d = 1; d < 64; d <<= 1) {
+        const unsigned va = __shfl_up(a, d), vb = __shfl_up(b, d);
+        if (j >= d) {
+          a += va;
+          b += vb;
+        }
+      }
+      pre[j + 1] = a;
+      preo[j + 1] = b;
+      if (j == 0) pre[0] = preo[0] = 0u;
+    }
+    __syncthreads();
+    auto owner = [&](const unsigned* p, unsigned k) {   // the lattice whose range holds k
+      int lo = 0, hi = njobs - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (p[mid] <= k) lo = mid;
+        else hi = mid - 1;
+      }
+      return lo;
+    };
+    // the other parity's flags, cleared for the next step's tile lists
+    const unsigned totalo = preo[njobs];
+    for (unsigned k = blockIdx.x * NT_NCI + threadIdx.x; k < totalo; k += gridDim.x * NT_NCI) {
+      const int j = owner(preo, k);
+      const Job<T, FS, GS>& jb = jobs[j];
+      const int par = (int)((jb.step + s) & 1);
+      jb.flags[1 - par][jb.list[1 - par][k - preo[j]]] = 0u;
+    }
+    const unsigned total = pre[njobs];
+    unsigned k = blockIdx.x;
+    if (k >= total) return;
+    int j = owner(pre, k);
+    NciHalo<DIM, T> halo;
+    {
+      const Job<T, FS, GS>& jb = jobs[j];
+      const int par = (int)((jb.step + s) & 1);
+      halo.load(jb.list[par][k - pre[j]], jb.phi, jb.geo);
+    }
+    unsigned act = 0;
+    while (k < total) {
+      const Job<T, FS, GS>& jb = jobs[j];
+      const int par = (int)((jb.step + s) & 1);
+      const unsigned kn = k + gridDim.x;
+      const int jn = kn < total ? owner(pre, kn) : j;
+      const bool same = kn < total && jn == j;
+      nci_tile_w<DIM, QH, T, false>(sm, jb.list[par][k - pre[j]], halo, same,
+                                    same ? jb.list[par][kn - pre[j]] : 0u, jb.phi, jb.J, nullptr, nullptr,
+                                    jb.geo, jb.np, act);
+      if (!same) {
+        // leaving this lattice: count its near-contact cells, and prefetch the next one's halo
+        act = wave_sum(act);
+        if ((threadIdx.x & 63) == 0 && act) atomicAdd(jb.cnt + 2, act);
+        act = 0;
+        if (kn < total) {
+          const Job<T, FS, GS>& jn_ = jobs[jn];
+          const int parn = (int)((jn_.step + s) & 1);
+          halo.load(jn_.list[parn][kn - pre[jn]], jn_.phi, jn_.geo);
+        }
+      }
+      k = kn;
+      j = jn;
+    }
+    return;
+  }
   for (int j = 0; j < njobs; ++j) {
     const Job<T, FS, GS>& jb = jobs[j];
     if (!jb.nci_on) continue;

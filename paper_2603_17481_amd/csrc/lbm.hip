@@ -827,8 +827,8 @@ struct Engine {
   // ---- serving: several lattices advanced by multi-domain launches
   using JobT = Job<T, FS, GS>;
 
-  static void batch_launch(hipStream_t st, const JobT* dj, int nj, int blocks, int s, bool o32) {
-    hipLaunchKernelGGL((k_phi_multi<DIM, T, FS, GS>), dim3((unsigned)blocks), dim3(NT), 0, st, dj, nj, s);
+  static void batch_launch(hipStream_t st, const JobT* dj, int nj, int blocks, int pblocks, int s, bool o32) {
+    hipLaunchKernelGGL((k_phi_multi<DIM, T, FS, GS>), dim3((unsigned)pblocks), dim3(NT), 0, st, dj, nj, s);
     hipLaunchKernelGGL((k_nci_multi<DIM, QH, T, FS, GS>), dim3(NCI_GRID), dim3(NT_NCI), 0, st, dj, nj, s);
     if (o32)
       hipLaunchKernelGGL((k_collide_multi<DIM, QH, T, FS, GS, true>), dim3((unsigned)blocks), dim3(NT), 0, st,
@@ -838,8 +838,9 @@ struct Engine {
                          st, dj, nj, s);
   }
 
-  // Table entry of one lattice whose blocks start at blk0 of the batch grid.
-  static JobT job_entry(lbm_ctx* c, int blk0) {
+  // Table entry of one lattice whose blocks start at blk0 of the batch grid
+  // (and at pblk0 of the phi pass's grid).
+  static JobT job_entry(lbm_ctx* c, int blk0, int pblk0) {
     JobT jb{};
     jb.pl = planes(c);
     jb.phi = (T*)c->phi();
@@ -856,6 +857,8 @@ struct Engine {
     jb.q_th = (T)c->p.q_th;
     jb.blk0 = blk0;
     jb.nblk = c->L.nblk;
+    jb.pblk0 = pblk0;
+    jb.pnblk = (c->L.nblk + PHI_PER - 1) / PHI_PER;
     jb.step = c->step;
     return jb;
   }
@@ -871,19 +874,20 @@ struct Engine {
     lbm_ctx* c0 = cs[0];
     hipStream_t st = c0->stream;
     for (int i = 1; i < count; ++i) HIP_OR_FAIL(c0, hipStreamSynchronize(cs[i]->stream));
-    int blocks = 0;
+    int blocks = 0, pblocks = 0;
     bool o32 = true;
     for (int i0 = 0; i0 < count; i0 += K) {
       JobChunk<JobT, K> chunk{};
       const int m = std::min(K, count - i0);
       for (int k = 0; k < m; ++k) {
-        chunk.j[k] = job_entry(cs[i0 + k], blocks);
+        chunk.j[k] = job_entry(cs[i0 + k], blocks, pblocks);
         blocks += cs[i0 + k]->L.nblk;
+        pblocks += chunk.j[k].pnblk;
         o32 = o32 && off32(cs[i0 + k]);
       }
       hipLaunchKernelGGL((k_put_jobs<JobT, K>), dim3(1), dim3(64), 0, st, table + i0, chunk, m);
     }
-    for (int sidx = 0; sidx < n; ++sidx) batch_launch(st, table, count, blocks, sidx, o32);
+    for (int sidx = 0; sidx < n; ++sidx) batch_launch(st, table, count, blocks, pblocks, sidx, o32);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return c0->fail(LBM_E_HIP, std::string("batch launch: ") + hipGetErrorString(e));
     HIP_OR_FAIL(c0, hipStreamSynchronize(st));
@@ -919,11 +923,12 @@ struct Engine {
     // previous call's upload from it has executed
     if (B->used) HIP_OR_FAIL(c0, hipEventSynchronize(B->copied));
     JobT* hj = (JobT*)B->hjobs;
-    int blocks = 0;
+    int blocks = 0, pblocks = 0;
     bool o32 = true;
     for (int i = 0; i < count; ++i) {
-      hj[i] = job_entry(cs[i], blocks);
+      hj[i] = job_entry(cs[i], blocks, pblocks);
       blocks += cs[i]->L.nblk;
+      pblocks += hj[i].pnblk;
       o32 = o32 && off32(cs[i]);
     }
     HIP_OR_FAIL(c0, hipMemcpyAsync(B->djobs, B->hjobs, B->bytes, hipMemcpyHostToDevice, st));
@@ -938,7 +943,7 @@ struct Engine {
         B->exec = nullptr;
         B->graph = nullptr;
         HIP_OR_FAIL(c0, hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-        for (int sidx = 0; sidx < BATCH_R; ++sidx) batch_launch(st, dj, count, blocks, sidx, o32);
+        for (int sidx = 0; sidx < BATCH_R; ++sidx) batch_launch(st, dj, count, blocks, pblocks, sidx, o32);
         hipLaunchKernelGGL((k_advance<T, FS, GS>), dim3((count + 63) / 64), dim3(64), 0, st,
                            (JobT*)B->djobs, count, BATCH_R);
         HIP_OR_FAIL(c0, hipStreamEndCapture(st, &B->graph));
@@ -948,7 +953,7 @@ struct Engine {
       }
       for (int k = 0; k < full; ++k) HIP_OR_FAIL(c0, hipGraphLaunch(B->exec, st));
     }
-    for (int sidx = 0; sidx < rem; ++sidx) batch_launch(st, dj, count, blocks, sidx, o32);
+    for (int sidx = 0; sidx < rem; ++sidx) batch_launch(st, dj, count, blocks, pblocks, sidx, o32);
     if (rem)
       hipLaunchKernelGGL((k_advance<T, FS, GS>), dim3((count + 63) / 64), dim3(64), 0, st,
                          (JobT*)B->djobs, count, rem);
