@@ -1884,21 +1884,25 @@ __global__ __launch_bounds__(NT) void k_cc_init(const T* __restrict__ phi, Geo g
 
 // Every cell of the set joins its neighbours of the set at the 4 (2D) / 13 (3D)
 // offsets that precede it in (z, y, x) order; with the periodic wrap this
-// covers each adjacent pair once.
-template <int DIM>
-__global__ __launch_bounds__(NT) void k_cc_merge(Geo geo, unsigned* __restrict__ L) {
+// covers each adjacent pair once.  Membership is read from phi (the test of
+// k_cc_init), with plain cached loads: only the label walks need the
+// device-scope atomic loads.
+template <int DIM, typename T>
+__global__ __launch_bounds__(NT) void k_cc_merge(const T* __restrict__ phi, Geo geo, int dispersed,
+                                                 unsigned* __restrict__ L) {
   int x, y, z;
   block_cell(swizzled_block(), geo, x, y, z);
   if (x >= geo.nx || y >= geo.ny) return;
   const Nbr nb(x, y, z, geo);
   const unsigned idx = (unsigned)nb(0, 0, 0);
-  if (cc_load(L + idx) == CC_NONE) return;
+  auto in = [&](unsigned j) { return dispersed ? (phi[j] > (T)0.5) : (phi[j] < (T)0.5); };
+  if (!in(idx)) return;
   const int dz0 = DIM == 3 ? -1 : 0;
   for (int dz = dz0; dz <= 0; ++dz)
     for (int dy = -1; dy <= (dz < 0 ? 1 : 0); ++dy)
       for (int dx = -1; dx <= ((dz < 0 || dy < 0) ? 1 : -1); ++dx) {
         const unsigned j = (unsigned)nb(dx, dy, dz);
-        if (cc_load(L + j) != CC_NONE) cc_unite(L, idx, j);
+        if (in(j)) cc_unite(L, idx, j);
       }
 }
 
@@ -1910,15 +1914,33 @@ __global__ __launch_bounds__(NT) void k_diag(const T* __restrict__ phi, Geo geo,
                                              double* __restrict__ partials) {
   int x, y, z;
   block_cell(swizzled_block(), geo, x, y, z);
-  double acc[NPART] = {};
+  double a0 = 0.0, a1 = 0.0, a6 = 0.0;
   if (x < geo.nx && y < geo.ny) {
     const unsigned idx = (unsigned)Nbr(x, y, z, geo)(0, 0, 0);
     const T p0 = phi[idx];
-    acc[0] = (double)p0;
-    acc[6] = isfinite((double)p0) ? 0.0 : 1.0;
-    acc[1] = L[idx] == idx ? 1.0 : 0.0;
+    a0 = (double)p0;
+    a6 = isfinite((double)p0) ? 0.0 : 1.0;
+    a1 = L[idx] == idx ? 1.0 : 0.0;
   }
-  block_partials(acc, partials);
+  // the three used slots only (the same sums, in the same order, as
+  // block_partials; the other slots are zero)
+  __shared__ double red[NT / 64][3];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  a0 = wave_sum(a0);
+  a1 = wave_sum(a1);
+  a6 = wave_sum(a6);
+  if (lane == 0) {
+    red[wv][0] = a0;
+    red[wv][1] = a1;
+    red[wv][2] = a6;
+  }
+  __syncthreads();
+  if (threadIdx.x < NPART) {
+    const int k = threadIdx.x, r = k == 0 ? 0 : (k == 1 ? 1 : (k == 6 ? 2 : -1));
+    double a = r < 0 ? 0.0 : red[0][r];
+    for (int j = 1; j < NT / 64; ++j) a = r < 0 ? a : a + red[j][r];
+    partials[blockIdx.x * NPART + k] = a;
+  }
 }
 
 // First stage of the reduction: block b reduces partials [b*chunk, (b+1)*chunk)
