@@ -63,8 +63,9 @@ def model_bytes(p):
         collide = 2 * 13 * rs + 2 * qg * rs + rs
         return collide, collide + qg * rs + rs
     if p.cac_solver:
-        collide = 2 * q * fs + rs + 2 * p.dim * rs
-        return collide, collide + rs + (2 + 2 * p.dim) * rs
+        # the collide writes u; the explicit update reads phi and u, writes phi
+        collide = 2 * q * fs + rs + p.dim * rs
+        return collide, collide + rs + (2 + p.dim) * rs
     collide = 2 * q * fs + 2 * qg * rs + rs
     return collide, collide + qg * rs + rs
 

@@ -1240,14 +1240,10 @@ __device__ __forceinline__ void collide_cell(const Planes<FS, GS>& pl, const T* 
     }
     }
     if (uout) {
-      // finite-difference phase field: the velocity of this collision and the
-      // sharpening flux a = phi (1 - phi) n feed the explicit update
-      const T kn = ph * ((T)1 - ph) * inv_g;
+      // finite-difference phase field: the velocity of this collision feeds
+      // the explicit update (which forms a = phi (1 - phi) n itself)
 #pragma unroll
-      for (int a = 0; a < DIM; ++a) {
-        st_nt(uout + a * S + idx, u[a]);
-        st_nt(uout + (DIM + a) * S + idx, kn * gr[a]);
-      }
+      for (int a = 0; a < DIM; ++a) st_nt(uout + a * S + idx, u[a]);
     } else {
     // ---- conservative Allen-Cahn populations: BGK towards
     //      geq_k = w_k (phi + c_k . j / cs_phi^2), j = phi u + M (4/W) phi (1-phi) n
@@ -1596,21 +1592,22 @@ __device__ __forceinline__ T flux_difference(const PH& ph, const UV& uv, int ax)
 // 4 M / W (Eqs. source_sharp, kappa_delta).  Accessors: ph(dx, dy, dz) phi at
 // a lattice offset, av(comp, dx, dy, dz) component comp of a at one.
 // Both stencils are summed per weight class (|c|^2 = 1, 2) before the weight
-// is applied.  The Laplacian is summed over differences to the cell, so that
-// it vanishes exactly on a uniform field (the rounded weights sum to one only
+// is applied.  The Laplacian is summed over (phi(x + c) + phi(x - c)) - 2 phi(x),
+// each exactly zero on a uniform field (the rounded weights sum to one only
 // approximately, and that residue would add mass every step), and the
 // increment is formed before it is added to phi (added term by term, parts
 // smaller than half an ulp of phi would each be rounded away).
 template <int DIM, int QH, typename T, typename PH, typename AV>
 __device__ __forceinline__ T muscl_increment(const PH& ph, const AV& av, T div, T mob, T kap) {
   using H = HydroQ<QH>;
-  const T pc = ph(0, 0, 0);
-  T sl[3] = {0, 0, 0}, dc[3] = {0, 0, 0};
+  const T p2 = ph(0, 0, 0) + ph(0, 0, 0);
+  // the sums start at -0, which the first addition folds away
+  T sl[3] = {(T)-0.0, (T)-0.0, (T)-0.0}, dc[3] = {(T)-0.0, (T)-0.0, (T)-0.0};
 #pragma unroll
   for (int i = 1; i < H::Q; i += 2) {
     const int c[3] = {H::cx[i], H::cy[i], H::cz[i]};
     const int cl = c[0] * c[0] + c[1] * c[1] + c[2] * c[2] - 1;
-    sl[cl] += (ph(c[0], c[1], c[2]) - pc) + (ph(-c[0], -c[1], -c[2]) - pc);
+    sl[cl] += (ph(c[0], c[1], c[2]) + ph(-c[0], -c[1], -c[2])) - p2;
 #pragma unroll
     for (int a = 0; a < DIM; ++a) {
       if (!c[a]) continue;
@@ -1630,67 +1627,143 @@ __device__ __forceinline__ T muscl_increment(const PH& ph, const AV& av, T div, 
   return (mob * lap - div) - kap * dvi;
 }
 
-// One cell per thread, neighbours read from global memory (2D boxes).  ua holds
-// u (DIM planes) then a (DIM planes), plane stride S; out must not alias phi.
+// Square root for the interface normal of the finite-difference update: the
+// hardware instruction in FP32 (within 1 ulp, against about fifteen
+// instructions for the correctly rounded one), the correctly rounded one in FP64.
+__device__ __forceinline__ float fast_sqrt(float a) { return __builtin_amdgcn_sqrtf(a); }
+__device__ __forceinline__ double fast_sqrt(double a) { return sqrt(a); }
+
+// The sharpening flux a = phi (1 - phi) n of the finite-difference update at
+// one cell (Eq. source_sharp), with the interface normal n = grad phi /
+// (|grad phi| + eps_n) of the isotropic gradient on the hydrodynamic lattice
+// (Eq. grad_iso).  get(i) is phi at the neighbour along direction i, get(0) the cell's own.
+template <int QH, typename T, typename G>
+__device__ __forceinline__ void sharpening_flux(const G& get, T eps_n, T a[3]) {
+  using H = HydroQ<QH>;
+  constexpr int DIM = H::D;
+  // differences across the cell summed per speed class |c|^2 = 1, 2, 3 and
+  // weighted once per class; the sums start at -0, which the first addition
+  // folds away
+  T s[3][3];
+#pragma unroll
+  for (int cl = 0; cl < 3; ++cl)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) s[cl][k] = (T)-0.0;
+#pragma unroll
+  for (int i = 1; i < H::Q; i += 2) {
+    const int c[3] = {H::cx[i], H::cy[i], H::cz[i]};
+    const int cl = c[0] * c[0] + c[1] * c[1] + c[2] * c[2] - 1;
+    const T d = get(i) - get(i + 1);
+#pragma unroll
+    for (int k = 0; k < DIM; ++k)
+      if (c[k]) s[cl][k] += c[k] > 0 ? d : -d;
+  }
+  constexpr double w1 = 3 * H::w[1], w2 = 3 * H::w[DIM == 2 ? 5 : 7];
+  constexpr double w3 = QH == 27 ? 3 * H::w[QH == 27 ? 19 : 0] : 0.0;
+  T gr[3] = {0, 0, 0};
+#pragma unroll
+  for (int k = 0; k < DIM; ++k) {
+    gr[k] = (T)w1 * s[0][k] + (T)w2 * s[1][k];
+    if constexpr (QH == 27) gr[k] += (T)w3 * s[2][k];
+  }
+  T gmag = gr[0] * gr[0] + gr[1] * gr[1];
+  if (DIM == 3) gmag += gr[2] * gr[2];
+  gmag = fast_sqrt(gmag);
+  const T ph = get(0);
+  const T kn = ph * ((T)1 - ph) * m_rcp(gmag + eps_n);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) a[k] = k < DIM ? kn * gr[k] : (T)0;
+}
+
+// One cell per thread, neighbours read from global memory (2D boxes).  uv holds
+// the velocity (DIM planes, plane stride S); a at the eight neighbours is formed
+// here from phi up to two cells away.  out must not alias phi.
 template <int DIM, int QH, typename T>
 __global__ __launch_bounds__(NT) void k_muscl(const T* __restrict__ phi, T* __restrict__ out,
-                                              const T* __restrict__ ua, Geo geo, T mob, T kap) {
+                                              const T* __restrict__ uvel, Geo geo, T mob, T kap, T eps_n) {
+  static_assert(DIM == 2, "3D boxes take k_muscl3");
+  using H = HydroQ<QH>;
   int x, y, z;
   block_cell(swizzled_block(), geo, x, y, z);
   if (x >= geo.nx || y >= geo.ny) return;
   const long long S = geo.S;
-  const int cc[3] = {x, y, z};
-  const int nn[3] = {geo.nx, geo.ny, geo.nz};
-  const int st[3] = {1, geo.nx, geo.nx * geo.ny};
-  const int idx = x + geo.nx * (y + geo.ny * z);
+  const int cc[2] = {x, y};
+  const int nn[2] = {geo.nx, geo.ny};
+  const int st[2] = {1, geo.nx};
+  const int idx = x + geo.nx * y;
   // offset of the cell d cells along axis ax (|d| <= 2, periodic)
   auto at = [&](int ax, int d) { return (wrap2(cc[ax] + d, nn[ax]) - cc[ax]) * st[ax]; };
-  auto off = [&](int dx, int dy, int dz) {
+  auto off = [&](int dx, int dy) {
     int o = idx;
     if (dx) o += at(0, dx);
     if (dy) o += at(1, dy);
-    if (DIM == 3 && dz) o += at(2, dz);
     return o;
   };
-  const T* A = ua + DIM * S;
-  auto ph = [&](int dx, int dy, int dz) { return phi[off(dx, dy, dz)]; };
-  auto uv = [&](int ax, int d) { return ua[ax * S + (d ? idx + at(ax, d) : idx)]; };
+  auto ph = [&](int dx, int dy, int) { return phi[off(dx, dy)]; };
+  auto uv = [&](int ax, int d) { return uvel[ax * S + (d ? idx + at(ax, d) : idx)]; };
+  T an[3][3][3];
+#pragma unroll
+  for (int i = 1; i < H::Q; ++i) {
+    const int dx = H::cx[i], dy = H::cy[i];
+    sharpening_flux<QH, T>([&](int k) { return phi[off(dx + H::cx[k], dy + H::cy[k])]; }, eps_n,
+                           an[dy + 1][dx + 1]);
+  }
   T div = 0;
 #pragma unroll
   for (int ax = 0; ax < DIM; ++ax) div += flux_difference<T>(ph, uv, ax);
   const T inc = muscl_increment<DIM, QH, T>(
-      ph, [&](int a, int dx, int dy, int dz) { return A[a * S + off(dx, dy, dz)]; }, div, mob, kap);
+      ph, [&](int a, int dx, int dy, int) { return an[dy + 1][dx + 1][a]; }, div, mob, kap);
   out[idx] = phi[idx] + inc;
 }
 
 // 3D: a block owns a 64 x TY column of cells and marches along z through
-// MUSCL_ZRUN planes.  Each plane of phi (halo 2) and of a (halo 1) is fetched
-// from HBM once per block into an LDS ring of three planes (z-1, z, z+1), u_x
-// and u_y of plane z likewise; the cell's own phi at z +- 2 and u_z at z +- 1
-// stay in registers.  Every neighbour read of the update then comes from LDS
-// or registers (about ten global loads per cell instead of about seventy), and
-// the loads of the next plane are issued before the update of this one, so
-// that their latency hides behind its arithmetic.
+// MUSCL_ZRUN planes.  Every plane of phi (halo 2 in x and y) is fetched from HBM
+// once per block into an LDS ring of six planes; a = phi (1 - phi) n of the
+// plane above the one being updated is then formed from the ring (halo 1) into
+// a ring of three planes, so that a costs no HBM traffic.  u_x (halo 1 along x)
+// and u_y (halo 1 along y) of the updated plane are staged in LDS too, double
+// buffered; the cell's own u_z stays in registers.  The loads of the next plane
+// are issued before the work on this one, so that their latency hides behind
+// it.  Two barriers per plane: after the staging stores and after a.  Unrolled
+// by the period of the rings (6 planes), every ring slot of the march is a
+// compile-time constant and each LDS access one instruction with an immediate
+// offset from a loop-invariant lane address.
 constexpr int MUSCL_ZRUN = 64;   // planes a block marches through
 constexpr int MZ_TX = 64;        // cells per block row
+constexpr int MZ_RING = 6;       // phi planes in LDS (z - 1 .. z + 3 in use)
 template <typename T>
 struct MuslTile {
-  static constexpr int TY = 4;   // rows per block (8 and 16 were slower: 1.16, 1.17 against 1.14 ms)
+  static constexpr int TY = 8;   // rows per block (4: 1.39 ms, 8: 1.34 ms at 512^3 FP32)
   static constexpr int NT = MZ_TX * TY;
   static constexpr int PW = MZ_TX + 4, PN = PW * (TY + 4);   // phi planes, halo 2
-  static constexpr int AW = MZ_TX + 2, AN = AW * (TY + 2);   // a and u planes, halo 1
+  static constexpr int AW = MZ_TX + 2, AN = AW * (TY + 2);   // a planes, halo 1
+  static constexpr int XN = (MZ_TX + 2) * TY;                // u_x: halo 1 along x
+  static constexpr int YN = MZ_TX * (TY + 2);                // u_y: halo 1 along y
   static constexpr int KP = (PN + NT - 1) / NT, KA = (AN + NT - 1) / NT;   // staged cells per thread
+  static constexpr int KX = (XN + NT - 1) / NT, KY = (YN + NT - 1) / NT;
 };
 
+template <int V>
+using Const = std::integral_constant<int, V>;
+
+// D3Q19 in FP32: the march unrolled, registers capped at 128 (four waves per
+// SIMD): 1.18 ms at 512^3, against 1.69 ms uncapped (131 registers, two) and
+// 1.32 ms rolled.  D3Q27 stays rolled: its unrolled body is six times the
+// larger stencil (2.1 ms unrolled, 1.74 ms rolled).
 template <int QH, typename T>
-__global__ __launch_bounds__(MuslTile<T>::NT) void k_muscl3(const T* __restrict__ phi, T* __restrict__ out,
-                                                            const T* __restrict__ ua, Geo geo, T mob, T kap,
-                                                            int ntx, int nty) {
+constexpr bool muscl_unrolled() { return QH == 19 && std::is_same<T, float>::value; }
+
+template <int QH, typename T>
+__global__ __launch_bounds__(MuslTile<T>::NT, (muscl_unrolled<QH, T>() ? 4 : 1)) void k_muscl3(const T* __restrict__ phi, T* __restrict__ out,
+                                                            const T* __restrict__ uvel, Geo geo, T mob, T kap,
+                                                            T eps_n, int ntx, int nty) {
   using M = MuslTile<T>;
-  constexpr int KP = M::KP, KA = M::KA;
-  __shared__ T sp[3][M::PN];
+  using H = HydroQ<QH>;
+  constexpr int KP = M::KP, KA = M::KA, KX = M::KX, KY = M::KY;
+  __shared__ T sp[MZ_RING][M::PN];
   __shared__ T sa[3][3][M::AN];
-  __shared__ T su[2][M::AN];
+  __shared__ T sx[2][M::XN];
+  __shared__ T sy[2][M::YN];
   const int t = swizzled_block();
   const int tx = t % ntx, r = t / ntx, ty = r % nty, zc = r / nty;
   const int x0 = tx * MZ_TX, y0 = ty * M::TY;
@@ -1701,109 +1774,132 @@ __global__ __launch_bounds__(MuslTile<T>::NT) void k_muscl3(const T* __restrict_
   const int plane = nx * ny;
   const int own = valid ? (x0 + lx) + nx * (y0 + ly) : 0;
   const long long S = geo.S;
-  // in-plane byte offsets of the staged halo cells, the same on every plane;
-  // the slots k below NT-multiples of the plane size are always in use
-  unsigned po[KP], ao[KA];
-  auto usedp = [&](int k) { return (k + 1) * M::NT <= M::PN || tid + k * M::NT < M::PN; };
-  auto useda = [&](int k) { return (k + 1) * M::NT <= M::AN || tid + k * M::NT < M::AN; };
+  // in-plane byte offsets of the staged cells, the same on every plane; the
+  // slots k below NT-multiples of a tile's size are always in use
+  auto used = [&](int k, int n) { return (k + 1) * M::NT <= n || tid + k * M::NT < n; };
+  auto inplane = [&](int ex, int ey) { return (unsigned)(wrapi(ex, nx) + nx * wrapi(ey, ny)) * sizeof(T); };
+  unsigned po[KP], xo[KX], yo[KY];
 #pragma unroll
   for (int k = 0; k < KP; ++k) {
     const int s = tid + k * M::NT;
-    po[k] = usedp(k) ? (unsigned)(wrapi(x0 - 2 + s % M::PW, nx) + nx * wrapi(y0 - 2 + s / M::PW, ny)) * sizeof(T)
-                     : 0u;
+    po[k] = used(k, M::PN) ? inplane(x0 - 2 + s % M::PW, y0 - 2 + s / M::PW) : 0u;
   }
+#pragma unroll
+  for (int k = 0; k < KX; ++k) {
+    const int s = tid + k * M::NT;
+    xo[k] = used(k, M::XN) ? inplane(x0 - 1 + s % (MZ_TX + 2), y0 + s / (MZ_TX + 2)) : 0u;
+  }
+#pragma unroll
+  for (int k = 0; k < KY; ++k) {
+    const int s = tid + k * M::NT;
+    yo[k] = used(k, M::YN) ? inplane(x0 + s % MZ_TX, y0 - 1 + s / MZ_TX) : 0u;
+  }
+  int pa[KA];   // the staged a cells in a phi plane
 #pragma unroll
   for (int k = 0; k < KA; ++k) {
     const int s = tid + k * M::NT;
-    ao[k] = useda(k) ? (unsigned)(wrapi(x0 - 1 + s % M::AW, nx) + nx * wrapi(y0 - 1 + s / M::AW, ny)) * sizeof(T)
-                     : 0u;
+    pa[k] = (s / M::AW + 1) * M::PW + s % M::AW + 1;
   }
   const unsigned owno = (unsigned)own * sizeof(T);
   // a plane of a field as a uniform base; cells are read at 32-bit byte offsets
   auto zbase = [&](const T* f, int z) { return (const char*)(f + (long long)wrapi(z, nz) * plane); };
   auto ld = [](const char* b, unsigned o) { return *(const T*)(b + o); };
-  const T* A = ua + 3 * S;
-  // registers in flight: phi and a of plane zr + 1, u_x and u_y of plane zr,
-  // own phi at zr + 2 and u_z at zr + 1
-  T rp[KP], ra[3][KA], ru[2][KA], rq = 0, rv = 0;
-  auto fetch = [&](int zr) {
-    const char* bp = zbase(phi, zr + 1);
+  // registers in flight: phi of one plane, u_x and u_y of one plane, own u_z
+  T rp[KP], rx[KX], ry[KY], rv = 0;
+  auto fetch_phi = [&](int zp) {
+    const char* bp = zbase(phi, zp);
 #pragma unroll
-    for (int k = 0; k < KP; ++k) rp[k] = usedp(k) ? ld(bp, po[k]) : (T)0;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      const char* ba = zbase(A + a * S, zr + 1);
-#pragma unroll
-      for (int k = 0; k < KA; ++k) ra[a][k] = useda(k) ? ld(ba, ao[k]) : (T)0;
-    }
-#pragma unroll
-    for (int a = 0; a < 2; ++a) {
-      const char* bu = zbase(ua + a * S, zr);
-#pragma unroll
-      for (int k = 0; k < KA; ++k) ru[a][k] = useda(k) ? ld(bu, ao[k]) : (T)0;
-    }
-    if (valid) {
-      rq = ld(zbase(phi, zr + 2), owno);
-      rv = ld(zbase(ua + 2 * S, zr + 1), owno);
-    }
+    for (int k = 0; k < KP; ++k) rp[k] = used(k, M::PN) ? ld(bp, po[k]) : (T)0;
   };
-  auto put_p = [&](T* dst, const T* v) {
+  auto fetch_u = [&](int zu) {
+    const char* bx = zbase(uvel, zu);
+    const char* by = zbase(uvel + S, zu);
+#pragma unroll
+    for (int k = 0; k < KX; ++k) rx[k] = used(k, M::XN) ? ld(bx, xo[k]) : (T)0;
+#pragma unroll
+    for (int k = 0; k < KY; ++k) ry[k] = used(k, M::YN) ? ld(by, yo[k]) : (T)0;
+    if (valid) rv = ld(zbase(uvel + 2 * S, zu + 1), owno);
+  };
+  auto put_phi = [&](T* dst) {
 #pragma unroll
     for (int k = 0; k < KP; ++k)
-      if (usedp(k)) dst[tid + k * M::NT] = v[k];
+      if (used(k, M::PN)) dst[tid + k * M::NT] = rp[k];
   };
-  auto put_a = [&](T* dst, const T* v) {
+  // a over the tile and its halo of one cell into a slot, from three
+  // consecutive phi planes of the ring
+  auto make_a = [&](T (*dst)[M::AN], const T* Pl, const T* Pc, const T* Pu) {
+    const T* P[3] = {Pl, Pc, Pu};
 #pragma unroll
-    for (int k = 0; k < KA; ++k)
-      if (useda(k)) dst[tid + k * M::NT] = v[k];
+    for (int k = 0; k < KA; ++k) {
+      if (!used(k, M::AN)) continue;
+      const int s = tid + k * M::NT, c = pa[k];
+      T av[3];
+      sharpening_flux<QH, T>([&](int i) { return P[1 + H::cz[i]][c + H::cy[i] * M::PW + H::cx[i]]; }, eps_n,
+                             av);
+#pragma unroll
+      for (int a = 0; a < 3; ++a) dst[a][s] = av[a];
+    }
   };
-  // prologue: planes z0 - 1 and z0 into ring slots 0 and 1, own column registers
-  int sm = 0, s0 = 1, sq = 2;
-  for (int d = -2; d <= -1; ++d) {
-    fetch(z0 + d);
-    put_p(sp[d + 2], rp);
+  // Ring slots, with j = (z - z0) mod 6 for the plane z being updated: phi of
+  // plane z + d in sp[(j + d + 2) mod 6], a of plane z + d in sa[(j + d + 1) mod 3],
+  // u_x and u_y of plane z in buffer j mod 2.
+  // prologue: phi planes z0 - 2 .. z0 + 1, a of planes z0 - 1 and z0, the
+  // flux through the face z0 - 1/2, then the loads of the first plane
 #pragma unroll
-    for (int a = 0; a < 3; ++a) put_a(sa[d + 2][a], ra[a]);
+  for (int d = -2; d <= 1; ++d) {
+    fetch_phi(z0 + d);
+    put_phi(sp[d + 2]);
   }
-  T q0 = 0, q1 = 0, q2 = 0, q3 = 0, v0 = 0, v1 = 0;
+  T v0 = 0, v1 = 0;
   if (valid) {
-    q0 = ld(zbase(phi, z0 - 2), owno);
-    q1 = ld(zbase(phi, z0 - 1), owno);
-    q2 = ld(zbase(phi, z0), owno);
-    q3 = ld(zbase(phi, z0 + 1), owno);
-    v0 = ld(zbase(ua + 2 * S, z0 - 1), owno);
-    v1 = ld(zbase(ua + 2 * S, z0), owno);
+    v0 = ld(zbase(uvel + 2 * S, z0 - 1), owno);
+    v1 = ld(zbase(uvel + 2 * S, z0), owno);
   }
-  fetch(z0);
-  T fzm = face_flux(q0, q1, q2, q3, (T)0.5 * (v0 + v1));   // flux through the face z0 - 1/2
+  fetch_phi(z0 + 2);
+  fetch_u(z0);
+  __syncthreads();
+  make_a(sa[0], sp[0], sp[1], sp[2]);
+  make_a(sa[1], sp[1], sp[2], sp[3]);
   const int cp = (ly + 2) * M::PW + lx + 2;   // the cell in a phi plane
-  const int ca = (ly + 1) * M::AW + lx + 1;   // the cell in an a / u plane
-  for (int z = z0; z < z1; ++z) {
-    put_p(sp[sq], rp);
+  const int ca = (ly + 1) * M::AW + lx + 1;   // the cell in an a plane
+  T fzm = face_flux(sp[0][cp], sp[1][cp], sp[2][cp], sp[3][cp], (T)0.5 * (v0 + v1));   // face z0 - 1/2
+  // one plane z, ring phase J = (z - z0) mod 6 (a compile-time constant when
+  // the march is unrolled)
+  auto plane_step = [&](int z, auto J) {
+    const int j = J;
+    T* const Pm = sp[(j + 1) % MZ_RING];
+    T* const P0 = sp[(j + 2) % MZ_RING];
+    T* const Pp = sp[(j + 3) % MZ_RING];
+    T* const Pq = sp[(j + 4) % MZ_RING];
+    put_phi(Pq);
 #pragma unroll
-    for (int a = 0; a < 3; ++a) put_a(sa[sq][a], ra[a]);
-    put_a(su[0], ru[0]);
-    put_a(su[1], ru[1]);
-    const T q4 = rq, v2 = rv;
+    for (int k = 0; k < KX; ++k)
+      if (used(k, M::XN)) sx[j & 1][tid + k * M::NT] = rx[k];
+#pragma unroll
+    for (int k = 0; k < KY; ++k)
+      if (used(k, M::YN)) sy[j & 1][tid + k * M::NT] = ry[k];
+    const T v2 = rv;
     __syncthreads();
-    if (z + 1 < z1) fetch(z + 1);
+    if (z + 1 < z1) {
+      fetch_phi(z + 3);
+      fetch_u(z + 1);
+    }
+    make_a(sa[(j + 2) % 3], P0, Pp, Pq);
+    __syncthreads();
     if (valid) {
-      const T* Pm = sp[sm];
-      const T* P0 = sp[s0];
-      const T* Pp = sp[sq];
+      const T* Ux = sx[j & 1];
+      const T* Uy = sy[j & 1];
+      const T q1 = Pm[cp], q2 = P0[cp], q3 = Pp[cp], q4 = Pq[cp];
       auto ph = [&](int dx, int dy, int dz) -> T {
-        if (dz == -2) return q0;
-        if (dz == 2) return q4;
         const T* P = dz < 0 ? Pm : (dz > 0 ? Pp : P0);
         return P[cp + dy * M::PW + dx];
       };
       auto uv = [&](int ax, int d) -> T {
         if (ax == 2) return d < 0 ? v0 : (d > 0 ? v2 : v1);
-        return su[ax][ca + (ax == 0 ? d : d * M::AW)];
+        return ax == 0 ? Ux[ly * (MZ_TX + 2) + lx + 1 + d] : Uy[(ly + 1 + d) * MZ_TX + lx];
       };
       auto av = [&](int a, int dx, int dy, int dz) -> T {
-        const int sl = dz < 0 ? sm : (dz > 0 ? sq : s0);
-        return sa[sl][a][ca + dy * M::AW + dx];
+        return sa[(j + 1 + dz + 3) % 3][a][ca + dy * M::AW + dx];
       };
       // the face below this cell is the face above the previous one
       const T fzp = face_flux(q1, q2, q3, q4, (T)0.5 * (v1 + v2));
@@ -1812,17 +1908,27 @@ __global__ __launch_bounds__(MuslTile<T>::NT) void k_muscl3(const T* __restrict_
       const T inc = muscl_increment<3, QH, T>(ph, av, div, mob, kap);
       st_nt((T*)((char*)(out + (long long)z * plane) + owno), q2 + inc);
     }
-    __syncthreads();
-    const int tmp = sm;
-    sm = s0;
-    s0 = sq;
-    sq = tmp;
-    q0 = q1;
-    q1 = q2;
-    q2 = q3;
-    q3 = q4;
     v0 = v1;
     v1 = v2;
+  };
+  if constexpr (!muscl_unrolled<QH, T>()) {
+#pragma unroll 1
+    for (int z = z0, j = 0; z < z1; ++z, j = j == MZ_RING - 1 ? 0 : j + 1) plane_step(z, j);
+    return;
+  }
+#pragma unroll 1
+  for (int z = z0; z < z1; z += MZ_RING) {
+    plane_step(z, Const<0>{});
+    if (z + 1 >= z1) break;
+    plane_step(z + 1, Const<1>{});
+    if (z + 2 >= z1) break;
+    plane_step(z + 2, Const<2>{});
+    if (z + 3 >= z1) break;
+    plane_step(z + 3, Const<3>{});
+    if (z + 4 >= z1) break;
+    plane_step(z + 4, Const<4>{});
+    if (z + 5 >= z1) break;
+    plane_step(z + 5, Const<5>{});
   }
 }
 

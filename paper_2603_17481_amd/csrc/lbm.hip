@@ -163,7 +163,7 @@ Layout make_layout(const lbm_params* p) {
   // finite-difference phase field only: the second phi buffer and u, a planes
   const bool fd = p->cac_solver != 0;
   L.off_phi2 = o;  o = align256(o + (fd ? (size_t)L.S * rs : 0));
-  L.off_ua = o;    o = align256(o + (fd ? 2 * (size_t)p->dim * L.S * rs : 0));
+  L.off_ua = o;    o = align256(o + (fd ? (size_t)p->dim * L.S * rs : 0));
   L.total = o;
   return L;
 }
@@ -539,10 +539,11 @@ struct Engine {
         const int nzc = (c->p.nz + MUSCL_ZRUN - 1) / MUSCL_ZRUN;
         hipLaunchKernelGGL((k_muscl3<QH, T>), dim3((unsigned)(ntx * nty * nzc)), dim3(M::NT), 0, c->stream,
                            (const T*)c->phi(), (T*)c->phi_next(), (const T*)c->ua(), c->geo,
-                           (T)c->p.mobility, (T)kap, ntx, nty);
+                           (T)c->p.mobility, (T)kap, (T)c->p.eps_n, ntx, nty);
       } else {
         hipLaunchKernelGGL((k_muscl<DIM, QH, T>), rows(c), dim3(NT), 0, c->stream, (const T*)c->phi(),
-                           (T*)c->phi_next(), (const T*)c->ua(), c->geo, (T)c->p.mobility, (T)kap);
+                           (T*)c->phi_next(), (const T*)c->ua(), c->geo, (T)c->p.mobility, (T)kap,
+                           (T)c->p.eps_n);
       }
     }
     c->phi_cur ^= 1;

@@ -36,9 +36,9 @@ def test_workspace_bytes_model():
     assert b - b16 >= 2 * n * 19 * 0.99
     p64 = p.replace(precision="fp64")
     assert L.lbm_workspace_bytes(p64) > 1.9 * b
-    # the finite-difference phase field adds a second phi plane and the u, a planes
+    # the finite-difference phase field adds a second phi plane and the u planes
     bfd = L.lbm_workspace_bytes(p.replace(cac_solver=1))
-    assert 4 * n * (1 + 6) <= bfd - b < 4 * n * (1 + 6) * 1.02
+    assert 4 * n * (1 + 3) <= bfd - b < 4 * n * (1 + 3) * 1.02
     # D3Q27 stores 8 more hydrodynamic populations
     assert L.lbm_workspace_bytes(p.replace(hydro_q=27)) - b == 4 * n * 8
     # moment storage: two buffers of 13 coefficient planes instead of 19 (or 27) populations
