@@ -40,20 +40,22 @@ METRIC = "MLUPS + % of HBM roofline per coupled step; served jobs/s + p99 latenc
 KERNEL_SRC = os.path.join(ROOT, "paper_2603_17481_amd", "csrc", "kernels.hpp")
 COUNTERS = [os.path.join(ROOT, "profiles", f) for f in
             ("collide_swarm512_fp32_counters.md", "kernels_swarm512_fp32_muscl.md",
-             "kernels_swarm512_fp32_d3q27.md", "kernels_swarm1024_fp16.md")]
+             "kernels_swarm512_fp32_d3q27.md", "kernels_swarm1024_fp16.md",
+             "kernels_swarm512_fp32_moments.md")]
 
 # Algorithmic bytes per cell (each population read once and written once, phi
 # read once; J read only in near-contact tiles, added per tile cell).
 #   collide, lattice Boltzmann phase field: f 2 Q fs + g 2 QG rs + phi rs
 #     (3D FP32 D3Q19: 152 + 56 + 4 = 212 B; FP16 f: 76 + 56 + 4 = 136 B; D3Q27: 276 B)
-#   collide, finite-difference phase field (Sec. 2.1.1): f 2 Q fs + phi rs + u, a 2 dim rs
-#     (3D FP32 D3Q19: 152 + 4 + 24 = 180 B)
+#   collide, finite-difference phase field (Sec. 2.1.1): f 2 Q fs + phi rs + u dim rs
+#     (3D FP32 D3Q19: 152 + 4 + 12 = 168 B)
 #   collide with moment storage (the hydrodynamic populations kept as 13 post-
 #     collision coefficients, two buffers): 2 13 rs + g 2 QG rs + phi rs
 #     (3D FP32: 104 + 56 + 4 = 164 B, D3Q19 and D3Q27 alike); each coefficient is
 #     read once from HBM, its reuse by the Q - 1 neighbours comes from the caches
 #   whole step: + the phi pass (g QG rs + phi rs; or phi rs for the flags alone)
-#     + the finite-difference update (phi, u, a read, phi written: (2 + 2 dim) rs)
+#     + the finite-difference update (phi and u read, phi written: (2 + dim) rs;
+#       it forms a = phi (1 - phi) n itself from the phi it stages)
 def model_bytes(p):
     rs = 8 if p.precision == "fp64" else 4
     fs = {"fp64": 8, "fp32": 4, "fp16": 2, "bf16": 2}[p.precision]
