@@ -1733,7 +1733,7 @@ constexpr int MZ_TX = 64;        // cells per block row
 constexpr int MZ_RING = 6;       // phi planes in LDS (z - 1 .. z + 3 in use)
 template <typename T>
 struct MuslTile {
-  static constexpr int TY = 8;   // rows per block (4: 1.39 ms, 8: 1.34 ms at 512^3 FP32)
+  static constexpr int TY = 8;   // rows per block: a is formed on 1.29 cells per cell (1.55 with 4 rows)
   static constexpr int NT = MZ_TX * TY;
   static constexpr int PW = MZ_TX + 4, PN = PW * (TY + 4);   // phi planes, halo 2
   static constexpr int AW = MZ_TX + 2, AN = AW * (TY + 2);   // a planes, halo 1
@@ -1747,9 +1747,9 @@ template <int V>
 using Const = std::integral_constant<int, V>;
 
 // D3Q19 in FP32: the march unrolled, registers capped at 128 (four waves per
-// SIMD): 1.18 ms at 512^3, against 1.69 ms uncapped (131 registers, two) and
-// 1.32 ms rolled.  D3Q27 stays rolled: its unrolled body is six times the
-// larger stencil (2.1 ms unrolled, 1.74 ms rolled).
+// SIMD): 1.12 ms at 512^3, against 1.69 ms uncapped (131 registers, two waves)
+// and 1.32 ms rolled.  D3Q27 stays rolled: its unrolled body is six times the
+// larger stencil (2.1 ms unrolled, 1.70 ms rolled).
 template <int QH, typename T>
 constexpr bool muscl_unrolled() { return QH == 19 && std::is_same<T, float>::value; }
 
@@ -2013,23 +2013,31 @@ __global__ __launch_bounds__(NT) void k_cc_merge(const T* __restrict__ phi, Geo 
 }
 
 // Per-block partials of the diagnostics: [0] sum phi, [1] roots of the
-// component labels (one per droplet), [6] non-finite phi.
+// component labels (one per droplet), [6] non-finite phi.  A block covers
+// DIAG_PER row blocks of the cell-wise grid (nblk of them in all), so that its
+// FP64 block reduction is paid once per DIAG_PER x NT cells.
+constexpr int DIAG_PER = 8;
 template <int DIM, typename T>
 __global__ __launch_bounds__(NT) void k_diag(const T* __restrict__ phi, Geo geo,
-                                             const unsigned* __restrict__ L,
+                                             const unsigned* __restrict__ L, int nblk,
                                              double* __restrict__ partials) {
-  int x, y, z;
-  block_cell(swizzled_block(), geo, x, y, z);
+  const int t = swizzled_block();
   double a0 = 0.0, a1 = 0.0, a6 = 0.0;
-  if (x < geo.nx && y < geo.ny) {
-    const unsigned idx = (unsigned)Nbr(x, y, z, geo)(0, 0, 0);
-    const T p0 = phi[idx];
-    a0 = (double)p0;
-    a6 = isfinite((double)p0) ? 0.0 : 1.0;
-    a1 = L[idx] == idx ? 1.0 : 0.0;
+#pragma unroll
+  for (int r = 0; r < DIAG_PER; ++r) {
+    const int lb = t * DIAG_PER + r;
+    if (lb >= nblk) break;
+    int x, y, z;
+    block_cell(lb, geo, x, y, z);
+    if (x < geo.nx && y < geo.ny) {
+      const unsigned idx = (unsigned)Nbr(x, y, z, geo)(0, 0, 0);
+      const T p0 = phi[idx];
+      a0 += (double)p0;
+      a6 += isfinite((double)p0) ? 0.0 : 1.0;
+      a1 += L[idx] == idx ? 1.0 : 0.0;
+    }
   }
-  // the three used slots only (the same sums, in the same order, as
-  // block_partials; the other slots are zero)
+  // the three used slots only (the other slots are zero)
   __shared__ double red[NT / 64][3];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   a0 = wave_sum(a0);

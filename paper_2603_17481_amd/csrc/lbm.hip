@@ -555,13 +555,14 @@ struct Engine {
                        c->dispersed, c->lab());
     hipLaunchKernelGGL((k_cc_merge<DIM, T>), rows(c), dim3(NT), 0, c->stream, (const T*)c->phi(), c->geo,
                        c->dispersed, c->lab());
-    hipLaunchKernelGGL((k_diag<DIM, T>), rows(c), dim3(NT), 0, c->stream, (const T*)c->phi(), c->geo,
-                       (const unsigned*)c->lab(), c->pb());
-    const int chunk = (c->L.nblk + RED1 - 1) / RED1;
+    const int nd = (c->L.nblk + DIAG_PER - 1) / DIAG_PER;   // k_diag blocks
+    hipLaunchKernelGGL((k_diag<DIM, T>), dim3((unsigned)nd), dim3(NT), 0, c->stream, (const T*)c->phi(), c->geo,
+                       (const unsigned*)c->lab(), c->L.nblk, c->pb());
+    const int chunk = (c->L.nblk + RED1 - 1) / RED1, chunkd = (nd + RED1 - 1) / RED1;
     hipLaunchKernelGGL(k_reduce_stage, dim3(RED1), dim3(NT), 0, c->stream, (const double*)c->pa(),
                        c->L.nblk, chunk, c->s1(0));
-    hipLaunchKernelGGL(k_reduce_stage, dim3(RED1), dim3(NT), 0, c->stream, (const double*)c->pb(),
-                       c->L.nblk, chunk, c->s1(1));
+    hipLaunchKernelGGL(k_reduce_stage, dim3(RED1), dim3(NT), 0, c->stream, (const double*)c->pb(), nd, chunkd,
+                       c->s1(1));
     hipLaunchKernelGGL(k_reduce, dim3(1), dim3(NT), 0, c->stream, (const double*)c->s1(0), RED1,
                        (const double*)c->s1(1), RED1,
                        (const unsigned*)(c->nci_on() ? c->cnt() + 2 : nullptr), c->red(slot));
