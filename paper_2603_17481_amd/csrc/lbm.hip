@@ -39,14 +39,19 @@ int q_phase(int dim) { return dim == 2 ? 9 : 7; }
 size_t real_size(int prec) { return prec == LBM_FP64 ? 8 : 4; }
 size_t fstore_size(int prec) { return prec == LBM_FP64 ? 8 : (prec == LBM_FP32 ? 4 : 2); }
 
+// Near-contact tile of a lattice: the kernels' NciTile of its dimension and
+// arithmetic type (FP64, or FP32 for every other precision).
+template <int DIM, typename T>
+void tile_dims_of(int* tx, int* ty, int* tz) {
+  *tx = NciTile<DIM, T>::TX;
+  *ty = NciTile<DIM, T>::TY;
+  *tz = NciTile<DIM, T>::TZ;
+}
 void tile_dims(int dim, int prec, int* tx, int* ty, int* tz) {
-  if (dim == 2) {
-    *tx = 16; *ty = 16; *tz = 1;
-  } else if (prec == LBM_FP64) {
-    *tx = 8; *ty = 8; *tz = 4;
-  } else {
-    *tx = 8; *ty = 8; *tz = 8;
-  }
+  if (dim == 2)
+    prec == LBM_FP64 ? tile_dims_of<2, double>(tx, ty, tz) : tile_dims_of<2, float>(tx, ty, tz);
+  else
+    prec == LBM_FP64 ? tile_dims_of<3, double>(tx, ty, tz) : tile_dims_of<3, float>(tx, ty, tz);
 }
 
 struct Layout {
