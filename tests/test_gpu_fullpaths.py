@@ -235,6 +235,23 @@ def test_muscl_tall_box_fp64(nz):
     g.close()
 
 
+def test_muscl_tall_box_fp32():
+    """FP32 (the update's march unrolled by its ring period) over three z chunks of
+    64, 64 and 22 planes, against the oracle at the FP32 bar after 300 steps."""
+    st = stacked_pair(150, precision="fp32")
+    announce("muscl 36x28x150 fp32 300 steps")
+    g = L.Lattice(st.params)
+    g.init_fields(st.phi, st.u)
+    g.step(300)
+    o = Oracle(st.params.replace(precision="fp64"))
+    o.init_fields(st.phi, st.u)
+    o.step(300)
+    errs = {f: rel_linf(getattr(g, f)(), getattr(o, f)()) for f in ("phi", "u")}
+    print(f"[gpu-case] errors {errs}", flush=True)
+    assert all(v <= FP32_BAR for v in errs.values()), errs
+    g.close()
+
+
 def test_muscl_swarm_512_fp32_one_step_on_sampled_subboxes():
     """The 512^3 FP32 swarm with the finite-difference phase field: one step of each
     AA parity on sampled sub-boxes, the state being the populations f and phi.

@@ -61,6 +61,23 @@ def test_fp64_near_contact(dim):
     assert abs(dg["mass_phi"] - do["mass_phi"]) <= 1e-12 * do["mass_phi"]
 
 
+@pytest.mark.parametrize("precision,steps,speed,bar", [("fp64", 40, 0.01, FP64_BAR), ("fp32", 1000, 0.0, FP32_BAR)])
+def test_ragged_box_3d(precision, steps, speed, bar):
+    """70 x 44 x 37: ragged against the 64 x 8 tiles of the 3D update in x and in y,
+    and 37 planes end its march one plane into the six-plane period of its ring
+    (FP32 marches unrolled by that period, FP64 rolled).  FP64: an approaching pair;
+    FP32: the pair at rest over 1000 steps, as the other FP32 tests (an approaching
+    pair drifts past the FP32 bar through rounding and transient partner flips)."""
+    p = W.Params(dim=3, nx=70, ny=44, nz=37, width=5.0, sigma=5e-3, a_rep=5e-3, density_ratio=10.0,
+                 cac_solver=1)
+    A = W.Sphere((20.37, 21.71, 18.29), 9.0, (speed, 0.0, 0.0))
+    B = W.Sphere((46.37, 21.37, 17.83), 9.0, (-speed, 0.0, 0.0))
+    st = W.spheres_state(p, [A, B], True, "ragged_pair")
+    g, o = run_pair(st, steps, precision)
+    assert_fields(g, o, bar, fields=("phi", "u"))
+    assert g.diagnostics()["n_droplets"] == o.diagnostics()["n_droplets"]
+
+
 def test_fp64_odd_steps_pure_diffusion_and_tiny_box():
     # odd step count (the state sits in the second phi buffer), no sharpening flux
     st = fd(near_contact_pair(2, nx=83), cac_compress=0)
