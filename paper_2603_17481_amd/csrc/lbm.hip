@@ -165,7 +165,7 @@ Layout make_layout(const lbm_params* p) {
   L.off_s1 = o;    o = align256(o + 2 * (size_t)RED1 * NPART * 8);
   L.off_red = o;   o = align256(o + (size_t)(HIST + 1) * 2 * NPART * 8);
   L.off_lab = o;   o = align256(o + (size_t)L.N * 4);
-  // finite-difference phase field only: the second phi buffer and u, a planes
+  // finite-difference phase field only: the second phi buffer and the u planes
   const bool fd = p->cac_solver != 0;
   L.off_phi2 = o;  o = align256(o + (fd ? (size_t)L.S * rs : 0));
   L.off_ua = o;    o = align256(o + (fd ? (size_t)p->dim * L.S * rs : 0));
