@@ -397,7 +397,11 @@ __global__ __launch_bounds__(NT) void k_phi(const GS* __restrict__ g, T* __restr
                                             unsigned* __restrict__ list,
                                             unsigned* __restrict__ cnt,
                                             unsigned* __restrict__ nci_count, int nci_on, T q_th) {
-  if (nci_on && blockIdx.x == 0 && threadIdx.x == 0) *nci_count = 0u;
+  if (nci_on && blockIdx.x == 0 && threadIdx.x == 0) {
+    nci_count[0] = 0u;                 // cells with a partner
+    nci_count[4] = nci_count[1];       // tiles the previous near-contact pass took
+    nci_count[1] = 0u;                 // tiles selected for this one
+  }
   int x, y, z;
   block_cell(swizzled_block(), geo, x, y, z);
   if (x >= geo.nx || y >= geo.ny) return;
@@ -876,6 +880,197 @@ __global__ __launch_bounds__(NT_NCI) __attribute__((amdgpu_waves_per_eu(sizeof(T
   if ((threadIdx.x & 63) == 0 && my_active) atomicAdd(nci_count, my_active);
 }
 
+// Tiles that cannot hold a partner, found before the near-contact pass.  A
+// gated cell can only pair with a gated cell of its window whose normal faces
+// its own (n(x).n(y) <= cos_opp).  k_nci_ranges gives each listed tile, per
+// sub-tile (the tile halved along each axis), the range [lo, hi] of each normal
+// component over its gated cells, from the operations k_nci uses for them;
+// k_nci_select bounds n(x).n(y) from below over the gated cells x of a tile
+// and the gated cells y of every sub-tile that the windows of its cells reach,
+// and lists the tile for k_nci unless the bound exceeds cos_opp by the margin
+// of k_nci's own sub-tile pruning.  A tile left out is flagged NCI_SKIPPED: no
+// cell of it has a partner, and the collide reads no J there.  Where most tiles
+// face another interface (dense swarms) the selection costs more than it saves:
+// it runs when the previous pass took at most half of its listed tiles, and on
+// probe steps; otherwise k_nci takes the whole list.  Either way the results
+// are the same.
+constexpr unsigned NCI_SKIPPED = 2u;
+
+// Whether this pass selects tiles: prev_listed and prev_taken are the tile
+// counts of the previous pass (its list, and the tiles it processed).
+__device__ __forceinline__ bool nci_selecting(unsigned prev_listed, unsigned prev_taken, int probe) {
+  return probe || prev_listed == 0u || 2u * prev_taken <= prev_listed;
+}
+
+template <int DIM, typename T>
+struct NciSub {
+  using TL = NciTile<DIM, T>;
+  static constexpr int SX = TL::TX / 2, SY = TL::TY / 2, SZ = DIM == 3 ? TL::TZ / 2 : 1;
+  static constexpr int NSUB = DIM == 3 ? 8 : 4, CPS = SX * SY * SZ;   // sub-tiles, cells per sub-tile
+  static_assert(CPS <= 64 && 64 % CPS == 0 && NSUB * CPS <= NT_NCI, "sub-tile lanes");
+};
+
+// Empty range: lo above hi (normal components lie in [-1, 1]).
+template <typename T>
+__device__ __forceinline__ void rng_empty(T r[6]) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    r[a] = (T)2;
+    r[3 + a] = (T)-2;
+  }
+}
+template <typename T>
+__device__ __forceinline__ void rng_merge(T r[6], const T* v) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    r[a] = v[a] < r[a] ? v[a] : r[a];
+    r[3 + a] = v[3 + a] > r[3 + a] ? v[3 + a] : r[3 + a];
+  }
+}
+// Minimum and maximum over groups of W consecutive lanes (W a power of two).
+template <int W, typename T>
+__device__ __forceinline__ void rng_lanes(T r[6]) {
+#pragma unroll
+  for (int o = 1; o < W; o <<= 1) {
+    T v[6];
+#pragma unroll
+    for (int a = 0; a < 6; ++a) v[a] = __shfl_xor(r[a], o, 64);
+    rng_merge(r, v);
+  }
+}
+
+// One block per listed tile (grid-stride): lane group sid of CPS lanes takes
+// sub-tile sid, one cell per lane; the ranges go to srng[(tile NSUB + sid) 6].
+template <int DIM, int QH, typename T>
+__global__ __launch_bounds__(NT_NCI) void k_nci_ranges(const T* __restrict__ phi, Geo geo,
+                                                       const unsigned* __restrict__ list,
+                                                       const unsigned* __restrict__ cnt, T* __restrict__ srng,
+                                                       T q_th, T eps_n, const unsigned* __restrict__ prev_listed,
+                                                       const unsigned* __restrict__ prev_taken, int probe) {
+  using TL = NciTile<DIM, T>;
+  using SB = NciSub<DIM, T>;
+  using L = HydroQ<QH>;
+  if (!nci_selecting(*prev_listed, *prev_taken, probe)) return;
+  const unsigned ntiles = *cnt;
+  const int sid = (int)threadIdx.x / SB::CPS, l = (int)threadIdx.x % SB::CPS;
+  for (unsigned k = blockIdx.x; k < ntiles; k += gridDim.x) {
+    const unsigned tile = list[k];
+    const int tx = (int)(tile % (unsigned)geo.ntx), ty = (int)((tile / (unsigned)geo.ntx) % (unsigned)geo.nty);
+    const int tz = (int)(tile / ((unsigned)geo.ntx * (unsigned)geo.nty));
+    T r[6];
+    rng_empty(r);
+    if (sid < SB::NSUB) {
+      const int x = tx * TL::TX + (sid & 1) * SB::SX + l % SB::SX;
+      const int y = ty * TL::TY + ((sid >> 1) & 1) * SB::SY + (l / SB::SX) % SB::SY;
+      const int z = DIM == 3 ? tz * TL::TZ + (sid >> 2) * SB::SZ + l / (SB::SX * SB::SY) : 0;
+      if (x < geo.nx && y < geo.ny && z < geo.nz) {
+        const Nbr nb(x, y, z, geo);
+        const T ph = phi[nb(0, 0, 0)];
+        const T pc = ph < (T)0 ? (T)0 : (ph > (T)1 ? (T)1 : ph);
+        if (pc * ((T)1 - pc) >= q_th) {
+          T gr[3], lap;
+          grad_lap<QH, T>([&](int i) { return phi[nb(L::cx[i], L::cy[i], L::cz[i])]; }, gr, lap);
+          T mag = gr[0] * gr[0] + gr[1] * gr[1];
+          if (DIM == 3) mag += gr[2] * gr[2];
+          const T inv = (T)1 / (m_sqrt(mag) + eps_n);
+          const T n[3] = {gr[0] * inv, gr[1] * inv, DIM == 3 ? gr[2] * inv : (T)0};
+#pragma unroll
+          for (int a = 0; a < 3; ++a) {
+            r[a] = n[a];
+            r[3 + a] = n[a];
+          }
+        }
+      }
+    }
+    rng_lanes<SB::CPS>(r);
+    if (sid < SB::NSUB && l == 0) {
+#pragma unroll
+      for (int a = 0; a < 6; ++a) srng[((size_t)tile * SB::NSUB + sid) * 6 + a] = r[a];
+    }
+  }
+}
+
+// One wave per listed tile (grid-stride over waves).  Along each axis the
+// distinct sub-tiles holding the cells within w of the tile (periodic) are
+// listed; the lanes share their product, merging the ranges of the sub-tiles
+// of listed tiles (flags of this parity, set by the phi pass).
+template <int DIM, typename T>
+__global__ __launch_bounds__(256) void k_nci_select(Geo geo, unsigned* __restrict__ flags,
+                                                    const unsigned* __restrict__ list,
+                                                    const unsigned* __restrict__ cnt, const T* __restrict__ srng,
+                                                    unsigned* __restrict__ alist, unsigned* __restrict__ acnt,
+                                                    int w, T cos_opp, const unsigned* __restrict__ prev_listed,
+                                                    const unsigned* __restrict__ prev_taken, int probe) {
+  using TL = NciTile<DIM, T>;
+  using SB = NciSub<DIM, T>;
+  constexpr int MAXS = 8;   // distinct sub-tiles per axis: at most (T + 2 w) / S + 1 with w <= 3, S >= 2
+  const unsigned ntiles = *cnt;
+  if (!nci_selecting(*prev_listed, *prev_taken, probe)) {
+    // the whole list
+    for (unsigned k = blockIdx.x * blockDim.x + threadIdx.x; k < ntiles; k += gridDim.x * blockDim.x)
+      alist[k] = list[k];
+    if (blockIdx.x == 0 && threadIdx.x == 0) *acnt = ntiles;
+    return;
+  }
+  const int lane = (int)(threadIdx.x & 63);
+  const unsigned nw = gridDim.x * (blockDim.x >> 6);
+  for (unsigned k = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); k < ntiles; k += nw) {
+    const unsigned tile = list[k];
+    const int tc[3] = {(int)(tile % (unsigned)geo.ntx), (int)((tile / (unsigned)geo.ntx) % (unsigned)geo.nty),
+                       (int)(tile / ((unsigned)geo.ntx * (unsigned)geo.nty))};
+    const int nn[3] = {geo.nx, geo.ny, geo.nz}, tt[3] = {TL::TX, TL::TY, TL::TZ}, ss[3] = {SB::SX, SB::SY, SB::SZ};
+    int sl[3][MAXS], ns[3];
+    bool over = false;   // more distinct sub-tiles than listed: select the tile
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      ns[a] = 0;
+      if (a >= DIM) {
+        sl[a][0] = 0;
+        ns[a] = 1;
+        continue;
+      }
+      const int lo = tc[a] * tt[a] - w, hi = min(tc[a] * tt[a] + tt[a], nn[a]) - 1 + w;
+      int prev = -1;
+      for (int c = lo; c <= hi; ++c) {
+        const int s = wrapi(c, nn[a]) / ss[a];
+        if (s != prev) {   // a repeat after a wrap only merges twice
+          if (ns[a] < MAXS)
+            sl[a][ns[a]++] = s;
+          else
+            over = true;
+        }
+        prev = s;
+      }
+    }
+    T u[6], own[6];
+    rng_empty(u);
+    rng_empty(own);
+    const int total = ns[0] * ns[1] * ns[2];
+    for (int q = lane; q < total; q += 64) {
+      const int sx = sl[0][q % ns[0]], sy = sl[1][(q / ns[0]) % ns[1]], sz = sl[2][q / (ns[0] * ns[1])];
+      const unsigned nt = (unsigned)(sx / 2 + geo.ntx * (sy / 2 + geo.nty * (sz / 2)));
+      if (flags[nt]) rng_merge(u, srng + ((size_t)nt * SB::NSUB + (sx & 1) + 2 * (sy & 1) + 4 * (sz & 1)) * 6);
+    }
+    if (lane < SB::NSUB) rng_merge(own, srng + ((size_t)tile * SB::NSUB + lane) * 6);
+    rng_lanes<64>(u);
+    rng_lanes<64>(own);
+    // lower bound of n(x).n(y): per component the least product of the two intervals
+    T bound = (T)0;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+      const T p0 = own[a] * u[a], p1 = own[a] * u[3 + a], p2 = own[3 + a] * u[a], p3 = own[3 + a] * u[3 + a];
+      const T m0 = p0 < p1 ? p0 : p1, m1 = p2 < p3 ? p2 : p3;
+      bound += m0 < m1 ? m0 : m1;
+    }
+    if (lane == 0) {
+      if (!over && bound > cos_opp + (T)1e-3)
+        flags[tile] = NCI_SKIPPED;
+      else
+        alist[atomicAdd(acnt, 1u)] = tile;
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // (b) fused collide + stream of both lattices (AA, in place)
 // ---------------------------------------------------------------------------
@@ -1126,7 +1321,7 @@ __device__ __forceinline__ void collide_cell(const Planes<FS, GS>& pl, const T* 
   T Jv[3] = {0, 0, 0};
   if (nci_on) {
     const unsigned tile = (unsigned)(x / TL::TX + geo.ntx * (y / TL::TY + geo.nty * (z / TL::TZ)));
-    if (flags[tile]) {
+    if (flags[tile] == 1u) {   // listed and not skipped (NCI_SKIPPED: no partner in the tile)
 #pragma unroll
       for (int a = 0; a < DIM; ++a) Jv[a] = *plane_at<OFF32>(J + a * S, idx);
     }

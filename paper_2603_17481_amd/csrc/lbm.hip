@@ -60,7 +60,7 @@ struct Layout {
   int rs, qc;   // population chunks: 2^rs rows, qc = nx 2^rs cells
   int bxs;      // cell-wise blocks are 2^bxs cells wide
   size_t off_f, off_g, off_phi, off_J, off_flags, off_list, off_cnt, off_pa, off_pb, off_s1,
-      off_red, off_lab, off_phi2, off_ua, total;
+      off_red, off_lab, off_phi2, off_ua, off_srng, off_alist, total;
 };
 
 bool valid_params(const lbm_params* p, std::string* why) {
@@ -169,6 +169,9 @@ Layout make_layout(const lbm_params* p) {
   const bool fd = p->cac_solver != 0;
   L.off_phi2 = o;  o = align256(o + (fd ? (size_t)L.S * rs : 0));
   L.off_ua = o;    o = align256(o + (fd ? (size_t)p->dim * L.S * rs : 0));
+  // near-contact tile selection: normal ranges per sub-tile, the selected tiles
+  L.off_srng = o;  o = align256(o + (size_t)L.ntiles * (p->dim == 3 ? 8 : 4) * 6 * rs);
+  L.off_alist = o; o = align256(o + (size_t)L.ntiles * 4);
   L.total = o;
   return L;
 }
@@ -215,7 +218,11 @@ struct lbm_ctx {
   void* J() const { return ws + L.off_J; }
   unsigned* flags(int k) const { return (unsigned*)(ws + L.off_flags) + (size_t)k * L.ntiles; }
   unsigned* list(int k) const { return (unsigned*)(ws + L.off_list) + (size_t)k * L.ntiles; }
-  unsigned* cnt() const { return (unsigned*)(ws + L.off_cnt); }   // [0],[1] lists, [2] chi count
+  // [0], [1] tile lists per parity, [2] cells with a partner, [3] tiles selected for
+  // the near-contact pass, [6] tiles the previous near-contact pass took
+  unsigned* cnt() const { return (unsigned*)(ws + L.off_cnt); }
+  void* srng() const { return ws + L.off_srng; }
+  unsigned* alist() const { return (unsigned*)(ws + L.off_alist); }
   double* pa() const { return (double*)(ws + L.off_pa); }
   double* pb() const { return (double*)(ws + L.off_pb); }
   double* s1(int k) const { return (double*)(ws + L.off_s1) + (size_t)k * RED1 * NPART; }
@@ -442,19 +449,33 @@ struct Engine {
                        (T)c->p.q_th);
   }
 
+  // Near-contact pass: normal ranges of the listed tiles, the tiles that can
+  // hold a partner (the others flagged NCI_SKIPPED), then k_nci on those.
   static void nci_pass(lbm_ctx* c, int par, int* chi, int* part) {
     if (!c->nci_on()) return;
     const int grid = std::min(NCI_GRID, std::max(1, c->L.ntiles));
     Timed tm(c, 1);
+    // selection statistics of the previous pass: its list count (reset by the
+    // collide after this pass) and the tiles it took (kept by the phi pass)
+    const unsigned* prev_listed = c->cnt() + (1 - par);
+    const unsigned* prev_taken = c->cnt() + 6;
+    const int probe = (c->step & 31) == 0 ? 1 : 0;
+    hipLaunchKernelGGL((k_nci_ranges<DIM, QH, T>), dim3(grid), dim3(NT_NCI), 0, c->stream, (const T*)c->phi(),
+                       c->geo, (const unsigned*)c->list(par), (const unsigned*)(c->cnt() + par), (T*)c->srng(),
+                       (T)c->p.q_th, (T)c->p.eps_n, prev_listed, prev_taken, probe);
+    const int sgrid = std::min(NCI_GRID, std::max(1, (c->L.ntiles + 3) / 4));   // four waves per block
+    hipLaunchKernelGGL((k_nci_select<DIM, T>), dim3(sgrid), dim3(256), 0, c->stream, c->geo, c->flags(par),
+                       (const unsigned*)c->list(par), (const unsigned*)(c->cnt() + par), (const T*)c->srng(),
+                       c->alist(), c->cnt() + 3, c->p.nci_window, (T)c->p.cos_opp, prev_listed, prev_taken, probe);
     if (chi) {
       hipLaunchKernelGGL((k_nci<DIM, QH, T, true>), dim3(grid), dim3(NT_NCI), 0, c->stream,
-                         (const T*)c->phi(), (T*)c->J(), chi, part, c->list(par), c->cnt() + par,
+                         (const T*)c->phi(), (T*)c->J(), chi, part, c->alist(), c->cnt() + 3,
                          c->flags(1 - par), c->list(1 - par), c->cnt() + (1 - par), c->cnt() + 2,
                          c->geo, c->nci);
     } else {
       hipLaunchKernelGGL((k_nci<DIM, QH, T, false>), dim3(grid), dim3(NT_NCI), 0, c->stream,
-                         (const T*)c->phi(), (T*)c->J(), (int*)nullptr, (int*)nullptr, c->list(par),
-                         c->cnt() + par, c->flags(1 - par), c->list(1 - par), c->cnt() + (1 - par),
+                         (const T*)c->phi(), (T*)c->J(), (int*)nullptr, (int*)nullptr, c->alist(),
+                         c->cnt() + 3, c->flags(1 - par), c->list(1 - par), c->cnt() + (1 - par),
                          c->cnt() + 2, c->geo, c->nci);
     }
   }
