@@ -44,7 +44,8 @@ COUNTERS = [os.path.join(ROOT, "profiles", f) for f in
              "kernels_swarm512_fp32_moments.md")]
 
 # Algorithmic bytes per cell (each population read once and written once, phi
-# read once; J read only in near-contact tiles, added per tile cell).
+# read once; J read only in the near-contact tiles holding a cell with a
+# partner, added per cell of those tiles).
 #   collide, lattice Boltzmann phase field: f 2 Q fs + g 2 QG rs + phi rs
 #     (3D FP32 D3Q19: 152 + 56 + 4 = 212 B; FP16 f: 76 + 56 + 4 = 136 B; D3Q27: 276 B)
 #   collide, finite-difference phase field (Sec. 2.1.1): f 2 Q fs + phi rs + u dim rs
@@ -372,12 +373,13 @@ def main():
     ms_step = ms_total / args.steps
     mlups = N * args.steps / (ms_total / 1e3) / 1e6
 
-    # near-contact tiles of the final state (J is read there): from phi on the host
-    phi = lat.phi()
-    pc = np.clip(phi, 0, 1)
-    gated = pc * (1 - pc) >= p.q_th
+    # J is read in the near-contact tiles that hold a cell with a partner (the
+    # tiles the method cannot leave out; the collide reads it in the selected
+    # tiles, a superset), counted from the final state's partner map
+    chi, _, _ = lat.nci()
     t = 8 if p.precision != "fp64" else 4
-    tiles = gated.reshape(p.nz // t, t, p.ny // 8, 8, p.nx // 8, 8).any(axis=(1, 3, 5)).sum()
+    tiles = (chi != 0).reshape(p.nz // t, t, p.ny // 8, 8, p.nx // 8, 8).any(axis=(1, 3, 5)).sum()
+    del chi
     tile_cells = int(tiles) * 8 * 8 * t
     real = 8 if p.precision == "fp64" else 4
     collide_bytes, step_bytes = model_bytes(p)
