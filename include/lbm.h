@@ -240,6 +240,14 @@ size_t lbm_state_bytes(const lbm_ctx* ctx);
 int lbm_save_state(lbm_ctx* ctx, void* host_buf, size_t bytes);
 int lbm_load_state(lbm_ctx* ctx, const void* host_buf, size_t bytes);
 
+/* Near-contact tile selection (Sec. 2.3 pruning, exact): before the
+ * near-contact pass, tiles whose gated normals cannot face a gated normal
+ * within the window are left out.  mode -1 (default): on lattices of at least
+ * 16384 near-contact tiles; 0: never; 1: always.  Results do not depend on the
+ * mode.  Synchronises the context's stream.  Returns LBM_OK or LBM_E_INVALID /
+ * LBM_E_HIP. */
+int lbm_nci_select(lbm_ctx* ctx, int mode);
+
 /* Testing hook: on != 0 makes the context's collide launches (k_collide,
  * k_collide_row, and k_collide_multi in every batch that holds the context)
  * use the instantiations that form element offsets in 64 bits, which a box

@@ -26,6 +26,10 @@ namespace {
 
 constexpr int HIST = 64;      // periodic diagnostics kept on the device
 constexpr int NCI_GRID = 4096;   // near-contact blocks (512^3 swarm: 0.291 ms against 0.314 with 2048)
+// Near-contact tiles from which a lattice selects them before the near-contact
+// pass (below, the two extra launches cost more than the pass saves: the steps of
+// 64^3 to 192^3 lattices are bound by launch latency).
+constexpr int NCI_SELECT_TILES = 16384;
 constexpr int RED1 = 512;     // first-stage blocks of the diagnostic reduction
 
 thread_local std::string g_create_error;
@@ -204,6 +208,7 @@ struct lbm_ctx {
   long k_cnt[5] = {0, 0, 0, 0, 0};
   int phi_cur = 0;   // finite-difference phase field: which phi buffer holds the state
   bool wide_offsets = false;   // lbm_force_wide_offsets: 64-bit offset kernels at any size
+  int nci_select = -1;         // lbm_nci_select: -1 by size, 0 never, 1 always
   int mom_cur = 0;   // moment storage: which coefficient buffer holds the state
 
   void* f() const { return ws + L.off_f; }
@@ -449,12 +454,32 @@ struct Engine {
                        (T)c->p.q_th);
   }
 
+  // Whether the near-contact pass selects tiles: on lattices of at least
+  // NCI_SELECT_TILES tiles (lbm_nci_select can force it on or off).
+  static bool nci_selects(const lbm_ctx* c) {
+    return c->nci_select >= 0 ? c->nci_select != 0 : c->L.ntiles >= NCI_SELECT_TILES;
+  }
+
   // Near-contact pass: normal ranges of the listed tiles, the tiles that can
   // hold a partner (the others flagged NCI_SKIPPED), then k_nci on those.
   static void nci_pass(lbm_ctx* c, int par, int* chi, int* part) {
     if (!c->nci_on()) return;
     const int grid = std::min(NCI_GRID, std::max(1, c->L.ntiles));
     Timed tm(c, 1);
+    if (!nci_selects(c)) {
+      // every listed tile (a small lattice's steps are bound by launches, not by this pass)
+      if (chi)
+        hipLaunchKernelGGL((k_nci<DIM, QH, T, true>), dim3(grid), dim3(NT_NCI), 0, c->stream,
+                           (const T*)c->phi(), (T*)c->J(), chi, part, c->list(par), c->cnt() + par,
+                           c->flags(1 - par), c->list(1 - par), c->cnt() + (1 - par), c->cnt() + 2,
+                           c->geo, c->nci);
+      else
+        hipLaunchKernelGGL((k_nci<DIM, QH, T, false>), dim3(grid), dim3(NT_NCI), 0, c->stream,
+                           (const T*)c->phi(), (T*)c->J(), (int*)nullptr, (int*)nullptr, c->list(par),
+                           c->cnt() + par, c->flags(1 - par), c->list(1 - par), c->cnt() + (1 - par),
+                           c->cnt() + 2, c->geo, c->nci);
+      return;
+    }
     // selection statistics of the previous pass: its list count (reset by the
     // collide after this pass) and the tiles it took (kept by the phi pass)
     const unsigned* prev_listed = c->cnt() + (1 - par);
@@ -1444,6 +1469,14 @@ int lbm_load_state(lbm_ctx* c, const void* buf, size_t bytes) {
   HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
   c->hist_count = 0;
   c->initialised = true;
+  return LBM_OK;
+}
+
+int lbm_nci_select(lbm_ctx* c, int mode) {
+  if (!c) return LBM_E_INVALID;
+  if (mode < -1 || mode > 1) return c->fail(LBM_E_INVALID, "nci_select mode must be -1, 0 or 1");
+  HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+  c->nci_select = mode;
   return LBM_OK;
 }
 

@@ -114,6 +114,7 @@ def load():
     lib.lbm_curvature_histogram.argtypes = [vp, C.c_double, C.c_double, C.c_double, C.c_int, lp]
     lib.lbm_component_volumes.argtypes = [vp, lp, C.c_long, lp]
     lib.lbm_force_wide_offsets.argtypes = [vp, C.c_int]
+    lib.lbm_nci_select.argtypes = [vp, C.c_int]
     _lib = lib
     return lib
 
@@ -325,6 +326,10 @@ class Lattice:
         if n.value > max_count:
             raise LBMError(-1, f"{n.value} components, more than max_count = {max_count}")
         return out[: n.value].copy()
+
+    def nci_select(self, mode: int):
+        """Near-contact tile selection: -1 by lattice size (default), 0 never, 1 always."""
+        self._check(self.lib.lbm_nci_select(self.h, int(mode)))
 
     def force_wide_offsets(self, on: bool = True):
         """Testing hook: run the collide kernels with 64-bit element offsets."""

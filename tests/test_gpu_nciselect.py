@@ -1,9 +1,11 @@
 """Selection of the near-contact tiles before the near-contact pass (single-lattice
-stepping).  A listed tile is left out only when a lower bound of n(x).n(y) over
-its gated cells and the gated cells their windows reach excludes every partner;
-the selection runs when the previous pass took at most half of its tiles and
-every 32 steps.  Both regimes must give exactly the oracle's near-contact maps
-and the state that batched stepping (which takes every listed tile) gives.
+stepping; on by default from 16384 tiles, forced on here with lbm_nci_select).  A
+listed tile is left out only when a lower bound of n(x).n(y) over its gated
+cells and the gated cells their windows reach excludes every partner; the
+selection runs when the previous pass took at most half of its tiles and every
+32 steps.  Both regimes must give exactly the oracle's near-contact maps, and the
+state that stepping without the selection and batched stepping (which takes
+every listed tile) give.
 """
 import numpy as np
 import pytest
@@ -33,23 +35,30 @@ def test_selection_matches_oracle_and_batch(make):
     p = st.params.replace(precision="fp64")
     announce(f"near-contact tile selection {st.kind} {p.nx}x{p.ny}x{p.nz} fp64 40 steps")
     g = L.Lattice(p)
+    g.nci_select(1)
     g.init_fields(st.phi, st.u)
     o = Oracle(p)
     o.init_fields(st.phi, st.u)
     b = L.Lattice(p)
     b.init_fields(st.phi, st.u)
+    h = L.Lattice(p)
+    h.nci_select(0)
+    h.init_fields(st.phi, st.u)
     for n in (1, 7, 32):   # steps 1, 8 (selection on the previous statistics) and 40 (a probe step before)
         g.step(n)
         o.step(n)
         L.lbm_batch_step([b], n)
+        h.step(n)
         chi_g, part_g, J_g = g.nci()
         chi_o, part_o, J_o = o.nci()
         print(f"[gpu-case] step {g.step_count}: cells with a partner {int(chi_o.sum())}", flush=True)
         assert np.array_equal(chi_g, chi_o) and np.array_equal(part_g, part_o)
         assert rel_linf(J_g, J_o) <= 1e-12
-        assert S.state_digest(g) == S.state_digest(b)
+        assert S.state_digest(g) == S.state_digest(b) == S.state_digest(h)
     assert chi_o.sum() > 0
     for f in ("phi", "u"):
         assert rel_linf(getattr(g, f)(), getattr(o, f)()) <= 1e-12
-    for lat in (g, b):
+    with pytest.raises(L.LBMError):
+        g.nci_select(2)
+    for lat in (g, b, h):
         lat.close()
