@@ -326,41 +326,54 @@ __device__ __forceinline__ T wave_min(T v) {
 // ---------------------------------------------------------------------------
 
 // phi of one cell from its incoming phase-field populations (AA parity PAR),
-// accumulated in FP64 (exact for FP32 populations) and rounded once; an
-// interfacial cell flags and lists its near-contact tile.
+// accumulated in FP64 (exact for FP32 populations) and rounded once.
+template <int DIM, int PAR, typename T, typename GS>
+__device__ __forceinline__ T phi_moment(const GS* __restrict__ g, const Geo& geo, int x, int y, int z) {
+  using P = Phase<DIM>;
+  double acc = 0.0;
+  const PopNbr<const GS> pn(g, x, y, z, geo, P::Q);
+  if constexpr (PAR == 0) {
+#pragma unroll
+    for (int i = 0; i < P::Q; ++i) acc += (double)ld_nt(pn.template at<false>(i, 0, 0, 0));
+  } else {
+#pragma unroll
+    for (int i = 0; i < P::Q; ++i)
+      acc += (double)ld_nt(pn.template at<false>(opp(i), -P::cx[i], -P::cy[i], -P::cz[i]));
+  }
+  return (T)acc;
+}
+
+// An interfacial cell (q = phi(1 - phi) at or above q_th, phi clamped to [0, 1])
+// flags its near-contact tile and lists it once.
+template <int DIM, typename T>
+__device__ __forceinline__ void phi_mark(T s, const Geo& geo, unsigned* __restrict__ flags,
+                                         unsigned* __restrict__ list, unsigned* __restrict__ cnt, T q_th,
+                                         int x, int y, int z) {
+  using TL = NciTile<DIM, T>;
+  const T pc = s < (T)0 ? (T)0 : (s > (T)1 ? (T)1 : s);
+  const T q = pc * ((T)1 - pc);
+  if (q >= q_th) {
+    const unsigned tile = (unsigned)(x / TL::TX + geo.ntx * (y / TL::TY + geo.nty * (z / TL::TZ)));
+    if (flags[tile] == 0u && atomicExch(&flags[tile], 1u) == 0u) list[atomicAdd(cnt, 1u)] = tile;
+  }
+}
+
+// phi of one cell (the moment, or the stored field of the finite-difference
+// phase field), and its near-contact tile mark.
 template <int DIM, int PAR, typename T, typename GS, bool GIVEN = false>
 __device__ __forceinline__ void phi_cell(const GS* __restrict__ g, T* __restrict__ phi, const Geo& geo,
                                          unsigned* __restrict__ flags, unsigned* __restrict__ list,
                                          unsigned* __restrict__ cnt, int nci_on, T q_th, int x, int y,
                                          int z) {
-  using P = Phase<DIM>;
-  using TL = NciTile<DIM, T>;
   const int idx = x + geo.nx * (y + geo.ny * z);
   T s;
   if constexpr (GIVEN) {
-    s = phi[idx];   // finite-difference phase field: phi is the stored field
+    s = phi[idx];
   } else {
-    double acc = 0.0;
-    const PopNbr<const GS> pn(g, x, y, z, geo, P::Q);
-    if constexpr (PAR == 0) {
-#pragma unroll
-      for (int i = 0; i < P::Q; ++i) acc += (double)ld_nt(pn.template at<false>(i, 0, 0, 0));
-    } else {
-#pragma unroll
-      for (int i = 0; i < P::Q; ++i)
-        acc += (double)ld_nt(pn.template at<false>(opp(i), -P::cx[i], -P::cy[i], -P::cz[i]));
-    }
-    s = (T)acc;
+    s = phi_moment<DIM, PAR, T, GS>(g, geo, x, y, z);
     st_nt(phi + idx, s);   // read again by other kernels only
   }
-  if (nci_on) {
-    const T pc = s < (T)0 ? (T)0 : (s > (T)1 ? (T)1 : s);
-    const T q = pc * ((T)1 - pc);
-    if (q >= q_th) {
-      const unsigned tile = (unsigned)(x / TL::TX + geo.ntx * (y / TL::TY + geo.nty * (z / TL::TZ)));
-      if (flags[tile] == 0u && atomicExch(&flags[tile], 1u) == 0u) list[atomicAdd(cnt, 1u)] = tile;
-    }
-  }
+  if (nci_on) phi_mark<DIM, T>(s, geo, flags, list, cnt, q_th, x, y, z);
 }
 
 // Tile of block for the fused collide + stream.  The hardware deals blocks to
@@ -2477,8 +2490,9 @@ struct Job {
 };
 
 // Row blocks per block of the multi-lattice phi pass: its per-cell work is a few
-// loads, so each block amortises its job-table lookup over several row blocks.
-constexpr int PHI_PER = 4;
+// loads, so each block amortises its job-table lookup over several row blocks,
+// and issues the loads of all of them before its first store.
+constexpr int PHI_PER = 8;
 // Lattices of a batch whose near-contact work is spread as one list (more fall
 // back to a loop over the lattices).
 constexpr int NCI_FLAT_JOBS = 64;
@@ -2505,6 +2519,34 @@ __device__ __forceinline__ int find_job_phi(const JT* __restrict__ jobs, int njo
   return lo;
 }
 
+// The PHI_PER row blocks of phi-pass block t: the cells past the lattice's end
+// load the clamped cell (in bounds) and store nothing.
+template <int DIM, int PAR, typename T, typename FS, typename GS>
+__device__ __forceinline__ void phi_rows(const Job<T, FS, GS>& jb, int t) {
+  T sv[PHI_PER];
+  int cx[PHI_PER], cy[PHI_PER], cz[PHI_PER];
+  bool ok[PHI_PER];
+#pragma unroll
+  for (int r = 0; r < PHI_PER; ++r) {
+    const int lb = (t - jb.pblk0) * PHI_PER + r;
+    int x, y, z;
+    block_cell(lb, jb.geo, x, y, z);
+    ok[r] = lb < jb.nblk && x < jb.geo.nx && y < jb.geo.ny;
+    cx[r] = min(x, jb.geo.nx - 1);
+    cy[r] = min(y, jb.geo.ny - 1);
+    cz[r] = min(z, jb.geo.nz - 1);
+  }
+#pragma unroll
+  for (int r = 0; r < PHI_PER; ++r) sv[r] = phi_moment<DIM, PAR, T, GS>(jb.pl.g, jb.geo, cx[r], cy[r], cz[r]);
+#pragma unroll
+  for (int r = 0; r < PHI_PER; ++r) {
+    if (!ok[r]) continue;
+    st_nt(jb.phi + (cx[r] + jb.geo.nx * (cy[r] + jb.geo.ny * cz[r])), sv[r]);
+    if (jb.nci_on)
+      phi_mark<DIM, T>(sv[r], jb.geo, jb.flags[PAR], jb.list[PAR], jb.cnt + PAR, jb.q_th, cx[r], cy[r], cz[r]);
+  }
+}
+
 template <int DIM, typename T, typename FS, typename GS>
 __global__ __launch_bounds__(NT) void k_phi_multi(const Job<T, FS, GS>* __restrict__ jobs, int njobs,
                                                   int s) {
@@ -2512,20 +2554,8 @@ __global__ __launch_bounds__(NT) void k_phi_multi(const Job<T, FS, GS>* __restri
   const Job<T, FS, GS>& jb = jobs[find_job_phi(jobs, njobs, t)];
   const int par = (int)((jb.step + s) & 1);
   if (jb.nci_on && t == jb.pblk0 && threadIdx.x == 0) jb.cnt[2] = 0u;
-#pragma unroll
-  for (int r = 0; r < PHI_PER; ++r) {
-    const int lb = (t - jb.pblk0) * PHI_PER + r;
-    if (lb >= jb.nblk) break;
-    int x, y, z;
-    block_cell(lb, jb.geo, x, y, z);
-    if (x >= jb.geo.nx || y >= jb.geo.ny) continue;
-    if (par == 0)
-      phi_cell<DIM, 0, T, GS>(jb.pl.g, jb.phi, jb.geo, jb.flags[0], jb.list[0], jb.cnt, jb.nci_on,
-                              jb.q_th, x, y, z);
-    else
-      phi_cell<DIM, 1, T, GS>(jb.pl.g, jb.phi, jb.geo, jb.flags[1], jb.list[1], jb.cnt + 1,
-                              jb.nci_on, jb.q_th, x, y, z);
-  }
+  if (par == 0) phi_rows<DIM, 0>(jb, t);
+  else phi_rows<DIM, 1>(jb, t);
 }
 
 // Near-contact pass of a batch.  Up to NCI_FLAT_JOBS lattices: the listed tiles

@@ -73,6 +73,32 @@ def test_batch_equals_alone(dim, precision):
         g.close()
 
 
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_batch_odd_shapes(precision):
+    """Batches of boxes whose widths and heights leave ragged blocks in the
+    collide and phi passes (one row wider than a block), at mixed AA parities:
+    each lattice bit for bit as alone."""
+    shapes = [(260, 6, 5), (96, 13, 8), (160, 7, 6), (24, 30, 10), (33, 17, 9)]
+    states = []
+    for k, (nx, ny, nz) in enumerate(shapes):
+        p = W.Params(dim=3, nx=nx, ny=ny, nz=nz, width=3.0, sigma=5e-3, a_rep=5e-3, density_ratio=10.0,
+                     precision=precision)
+        A = W.Sphere((nx / 2 + 0.3, ny / 2 + 0.2, nz / 2 - 0.1), min(ny, nz) / 3, (0.01, -0.005, 0.002))
+        states.append(W.spheres_state(p, [A], True, f"odd_box_{k}"))
+    pre = [0, 1, 0, 3, 2]
+    announce(f"batch odd shapes {precision}")
+    alone = build(states, pre)
+    mixed = build(states, pre)
+    for n in (9, 8, 1):
+        for g in alone:
+            g.step(n)
+        L.lbm_batch_step(mixed, n)
+        for k, (ga, gm) in enumerate(zip(alone, mixed)):
+            assert same_state(ga, gm), f"lattice {shapes[k]} differs after {gm.step_count} steps"
+    for g in alone + mixed:
+        g.close()
+
+
 def test_batch_subset_order_and_destroy():
     """Different subsets and orders of the same contexts reuse or rebuild their
     cached graphs; destroying a context drops its cached batches."""
